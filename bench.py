@@ -1,0 +1,268 @@
+"""Benchmark of the per-block BTO path on one MI355X.
+
+One step = one interval of the hot path over the resident input: seed the
+lattice, advance every live particle by the interval's RK4 steps (one per
+cycle) with boundary termination and compaction, and write the flow map.
+Workload: the 128^3 time-varying ABC block with noise (101 cycles, dt 0.05,
+64^3 seeds at stride 2, 100-step interval), FP32 grids resident in HBM.
+
+Prints one JSON line: particle-RK4-steps/s of the whole step, the roofline of
+the dominant kernel (the fused advection launch, timed with HIP events on the
+stream it runs on), and the FP64 oracle timed on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-RK4-steps/s on 1 MI355X + %HBM peak; FP32 vs FP16 field at stated err"
+HBM_PEAK_GBS = 8000.0
+STATE_BYTES = 40          # 16 B state + 4 B id, read once and written once per launch
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "advect_f32_abc128_traffic.json")
+KERNEL_SOURCES = ["paper_2004_02003_amd/csrc/bto_device.h", "paper_2004_02003_amd/csrc/advect.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def field_bytes_per_point(dt: str) -> int:
+    return 12 if dt == "f32" else 6
+
+
+def launch_plan(n_steps: int, kmax: int = 32):
+    nl = (n_steps + kmax - 1) // kmax
+    return [n_steps // nl + (1 if l < n_steps % nl else 0) for l in range(nl)]
+
+
+def algorithmic_bytes(per_launch, dt: str, stride: int):
+    """Bytes the fused launches must move: per particle-step one new grid level
+    over the points its cell touches (stride^3 points per seed at the lattice
+    density, i.e. 8 at stride 2), the first level once per launch, and the
+    particle state in and out once per launch."""
+    bpt = field_bytes_per_point(dt) * (stride ** 3 if stride <= 2 else 8)
+    total = 0
+    for live_in, psteps in per_launch:
+        total += bpt * (psteps + live_in) + STATE_BYTES * live_in
+    return total
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="abc_128")
+    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the per-block BTO path has no cross-GPU work "
+              "(blocks are independent); run one process per block instead.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle
+    from bto_inputs.workloads import WORKLOADS
+    from paper_2004_02003_amd import Context, grid_to_device
+    from paper_2004_02003_amd import _lib
+
+    _lib.load()
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    wl = WORKLOADS[args.workload]
+    dt = args.dtype
+    log(f"workload {wl.name}: generating {wl.n_cycles} grids {wl.n} ({dt})")
+    t0 = time.time()
+    series = wl.make_field()
+    grids_host = series.grids(dt) if (not args.no_cpu_baseline or not args.no_variants) else None
+    dev = [grid_to_device(g, dt) for g in (grids_host if grids_host is not None else series.grids(dt))]
+    torch.cuda.synchronize()
+    log(f"grids resident ({sum(g.numel() * g.element_size() for g in dev) / 2**30:.2f} GiB) in {time.time() - t0:.1f}s")
+    times = np.asarray(series.times, dtype=np.float64)
+    N = wl.n_steps
+    ptrs = [g.data_ptr() for g in dev]
+    dcode = {"f32": _lib.BTO_F32, "f16": _lib.BTO_F16, "bf16": _lib.BTO_BF16}[dt]
+
+    ctx = Context(wl.n, wl.n_seeds)
+    P = ctx.seed(wl.stride)
+    out = ctx.flowmap()
+
+    # per-launch live counts and particle-steps (untimed pass, one call per launch)
+    plan = launch_plan(N)
+    per_launch = []
+    q = 0
+    ctx.seed(wl.stride)
+    prev = ctx.stats()
+    for K in plan:
+        ctx.advect_ptrs(ptrs[q:q + K + 1], times[q:q + K + 1], dcode)
+        st = ctx.stats()
+        per_launch.append((prev["n_live"], st["particle_steps"] - prev["particle_steps"]))
+        prev = st
+        q += K
+    psteps_interval = prev["particle_steps"]
+    n_valid = prev["n_live"]
+    log(f"{P} seeds, {psteps_interval} particle-steps per interval, {n_valid} valid at the end, "
+        f"{len(plan)} launches of {plan} steps")
+
+    def one_step(ev=None):
+        ctx.seed(wl.stride)
+        if ev is not None:
+            ev[0].record()
+        ctx.advect_ptrs(ptrs, times, dcode)
+        if ev is not None:
+            ev[1].record()
+        ctx.flowmap(out=out)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        one_step(evs[k])
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    adv_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    st = ctx.stats()
+    assert st["particle_steps"] == psteps_interval, "particle-step count changed between intervals"
+    ms_per_step = 1e3 * t_total / args.steps
+    value = psteps_interval * args.steps / t_total
+    launch_ms = adv_ms / len(plan)
+    bytes_interval = algorithmic_bytes(per_launch, dt, wl.stride)
+    achieved = bytes_interval / len(plan) / (launch_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("kernel_hash") == kernel_hash() and rec.get("workload") == wl.name and rec.get("dtype") == dt:
+            traffic = rec.get("bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"advect_kernel<{dt},linear>", "launches_per_step": len(plan),
+            "avg_launch_ms": round(launch_ms, 4),
+            "algorithmic_bytes_per_launch": int(bytes_interval / len(plan))}
+    log(f"{value:.3e} particle-steps/s, {ms_per_step:.3f} ms per interval, advect {adv_ms:.3f} ms, "
+        f"{achieved:.0f} GB/s algorithmic")
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "particle-RK4-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
+        "data": "synthetic (seeded analytic ABC flow + Gaussian noise; no dataset)",
+        "config": {"workload": wl.name, "n": list(wl.n), "cycles": wl.n_cycles, "dt": wl.dt,
+                   "stride": wl.stride, "seeds": P, "interval_steps": N, "storage": dt,
+                   "particle_steps_per_interval": int(psteps_interval), "valid_at_end": int(n_valid)},
+        "advect_only": {"value": round(psteps_interval / (adv_ms * 1e-3), 1), "ms": round(adv_ms, 4)},
+        "roofline": roof,
+    }
+
+    # in situ form: one call per cycle with the two resident grids
+    if not args.no_variants:
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+        for r in range(4):
+            ctx.seed(wl.stride)
+            if r >= 1:
+                ev[r - 1][0].record()
+            for s_ in range(N):
+                ctx.advect_ptrs(ptrs[s_:s_ + 2], times[s_:s_ + 2], dcode)
+            if r >= 1:
+                ev[r - 1][1].record()
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        result["insitu_per_cycle"] = {"value": round(psteps_interval / (ms * 1e-3), 1), "ms": round(ms, 4),
+                                      "launches": N}
+    ctx.close()
+
+    # FP16 / BF16 storage of the same field, with the error against the FP64 oracle
+    if not args.no_variants:
+        variants = {}
+        ids = np.arange(0, P, 97)
+        seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
+        log("oracle on the FP64 grids for the error statement")
+        g64 = [series.make(c) for c in range(series.n_cycles)]
+        o64 = oracle.flowmap(oracle.Field(wl.n, g64), times, seeds, N)
+        del g64
+        for vdt in ("f32", "f16", "bf16"):
+            gh = series.grids(vdt) if vdt != dt else grids_host
+            dv = [grid_to_device(g, vdt) for g in gh]
+            vptr = [g.data_ptr() for g in dv]
+            vcode = {"f32": _lib.BTO_F32, "f16": _lib.BTO_F16, "bf16": _lib.BTO_BF16}[vdt]
+            with Context(wl.n, wl.n_seeds) as c2:
+                c2.seed(wl.stride)
+                c2.advect_ptrs(vptr, times, vcode)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                tt = []
+                for r in range(5):
+                    c2.seed(wl.stride)
+                    e0.record()
+                    c2.advect_ptrs(vptr, times, vcode)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    tt.append(e0.elapsed_time(e1))
+                fm = c2.flowmap()
+                stv = c2.stats()
+                torch.cuda.synchronize()
+                end = fm["end"].cpu().numpy()[ids]
+                flag = fm["flag"].cpu().numpy()[ids]
+            both = (flag == 0) & (o64["flag"] == 0)
+            err = np.linalg.norm(end[both] - o64["end"][both], axis=1)
+            variants[vdt] = {
+                "advect_value": round(stv["particle_steps"] / (np.median(tt) * 1e-3), 1),
+                "advect_ms": round(float(np.median(tt)), 4),
+                "err_vs_fp64_cells": {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)),
+                                      "max": float(err.max()), "n": int(both.sum()),
+                                      "flag_disagree": int((flag != o64["flag"]).sum())}}
+            del dv
+            torch.cuda.empty_cache()
+        result["storage_variants"] = variants
+
+    if not args.no_cpu_baseline:
+        ids = np.arange(0, P, 4)
+        seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        F = oracle.Field(wl.n, grids_host, dtype=dt)
+        log(f"oracle CPU baseline on {len(ids)} seeds, {threads} threads")
+        tc = time.perf_counter()
+        o = oracle.flowmap(F, times, seeds, N, nthreads=threads)
+        tc = time.perf_counter() - tc
+        ps = int(np.where(o["flag"] == 0, N, o["exit"] + 1).sum())
+        result["cpu_baseline"] = {"value": round(ps / tc, 1), "unit": "particle-RK4-steps/s", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": f"every 4th seed of {wl.name} ({len(ids)} seeds x {N} steps, "
+                                            f"{ps} particle-steps, {tc:.1f} s), FP64, OpenMP"}
+
+    if args.copy_probe:
+        x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x 1 GiB device copy done")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,136 @@
+/*
+ * bto.h -- C-ABI of the per-block Boundary Termination Optimization (BTO)
+ * advection library for AMD Instinct MI355X (gfx950).
+ *
+ * The method (Sane et al., "Scalable In Situ Lagrangian Flow Map Extraction",
+ * Section 3.1): on one process's block of a time-varying velocity field,
+ * seed basis-flow particles on a uniform lattice, advance each with one
+ * fourth-order Runge-Kutta step per simulation cycle, terminate every particle
+ * whose trajectory reaches the block boundary, and at the end of the interval
+ * store the flow map F_{t0}^{t}(x0) (Section 2.1) of the particles that stayed
+ * inside.  No communication is involved: every block is independent.
+ *
+ * Conventions shared by every entry point
+ *  - Coordinates: world coordinates at the boundary.  A block has n[d] grid
+ *    points per axis (n[d] >= 2, n[d] <= 1024), point (i,j,k) at
+ *    origin + spacing * (i,j,k).  The block is the closed box spanned by its
+ *    grid points; a point on a face is inside.
+ *  - Velocity grids: one per cycle, array-of-structures (vx,vy,vz) per point,
+ *    x fastest then y then z: element ((k*n[1] + j)*n[0] + i)*3 + d.  Storage
+ *    type float32, float16 or bfloat16 (bto_dtype); values in world units per
+ *    unit time.  Between cycles n and n+1 the field is linear in time; inside
+ *    a cell it is trilinear in space.
+ *  - Memory: every d_* pointer is device memory of the context's device.
+ *    Velocity grids are borrowed: they must stay alive and unchanged until the
+ *    work enqueued on `stream` has completed.  Outputs are caller-allocated.
+ *    The context owns all particle state.
+ *  - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *    Calls only enqueue work and return, unless stated otherwise.
+ *  - Errors: arguments are validated before anything is enqueued.  Return
+ *    codes below; bto_last_error gives the message of the last failure.  An
+ *    asynchronous device fault surfaces as BTO_EHIP on a later call.
+ *  - Threads: one context per host thread at a time.
+ */
+#ifndef BTO_H
+#define BTO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bto_ctx bto_ctx;
+
+enum bto_status {
+    BTO_OK = 0,
+    BTO_EINVAL = -1, /* bad argument (null pointer, size, time order, dtype) */
+    BTO_ENOMEM = -2, /* device allocation failed                             */
+    BTO_EHIP = -3,   /* HIP runtime error (launch failure, earlier fault)    */
+    BTO_ESTATE = -4, /* call out of order (e.g. advect before seed)          */
+    BTO_ERANGE = -5  /* count above the context's capacity                   */
+};
+
+typedef enum { BTO_F32 = 0, BTO_F16 = 1, BTO_BF16 = 2 } bto_dtype;
+
+/* Time interpolation inside one RK4 step (flags of bto_advect_interval).
+ * LINEAR: stage velocities at t_n, t_n + h/2, t_n + h/2, t_n + h interpolate
+ * linearly between the grids of cycles n and n+1.  FROZEN: every stage reads
+ * the grid of cycle n (the single-time-step in situ constraint of Section 2.2). */
+enum { BTO_TIME_LINEAR = 0, BTO_TIME_FROZEN = 1 };
+
+/* Per-seed outcome in the flow map. */
+enum { BTO_VALID = 0, BTO_TERMINATED = 1, BTO_INVALID = 2 };
+
+typedef struct {
+    int32_t n[3];        /* grid points per axis                    */
+    double origin[3];    /* world position of grid point (0,0,0)    */
+    double spacing[3];   /* grid spacing per axis (> 0)             */
+} bto_block;
+
+typedef struct {
+    int64_t n_seeds;         /* seeds placed by the last bto_seed*                    */
+    int64_t n_live;          /* particles still advancing                             */
+    int64_t particle_steps;  /* RK4 steps attempted since seeding (live particles,    */
+                             /* including each particle's terminating step)           */
+    int32_t steps_done;      /* steps advanced in the current interval                */
+    int32_t reserved;
+} bto_stats_t;
+
+/* Create a context for one block on HIP device `device`, with room for
+ * `max_particles` seeds (device memory ~100 B per seed is allocated here).
+ * Returns BTO_EINVAL for bad sizes, BTO_ENOMEM if allocation fails. */
+int bto_create(const bto_block *blk, int64_t max_particles, int32_t device, bto_ctx **out);
+
+/* Release the context and its device memory (synchronizes its device). */
+int bto_destroy(bto_ctx *ctx);
+
+/* Message of the last failing call on this context (never NULL). */
+const char *bto_last_error(const bto_ctx *ctx);
+
+/* Start a new interval with a uniform seed lattice (the 1:X data reduction of
+ * Section 2.3: one seed per stride^3 grid points).  Seed coordinate per axis,
+ * in cell units from the block origin: offset[d] + stride * m, m = 0, 1, ...
+ * while <= n[d] - 1; offset3 == NULL means (stride - 1) / 2 on every axis.
+ * Seed ids are the lattice linear index, x fastest.  *n_seeds_out (may be
+ * NULL) receives the count.  BTO_ERANGE if it exceeds max_particles. */
+int bto_seed(bto_ctx *ctx, int32_t stride, const double *offset3, int64_t *n_seeds_out, void *stream);
+
+/* Start a new interval with caller-given seeds: d_xyz is n x 3 doubles (world
+ * coordinates, device memory), seed id = row index.  Seeds outside the block
+ * are TERMINATED at exit step 0. */
+int bto_seed_explicit(bto_ctx *ctx, const double *d_xyz, int64_t n, void *stream);
+
+/* Advance every live particle by n_steps RK4 steps (Section 3.1), one per
+ * cycle, terminating at the block boundary.  d_fields is a HOST array of
+ * n_steps + 1 device pointers to velocity grids of the consecutive cycles
+ * c0 .. c0 + n_steps, times (host) their n_steps + 1 strictly increasing
+ * times; step s uses h = times[s+1] - times[s].  May be called repeatedly
+ * within one interval (e.g. once per cycle with two grids): steps accumulate
+ * and exit steps count from the seeding.  flags: BTO_TIME_LINEAR or
+ * BTO_TIME_FROZEN.  Termination rule: the stage points y2, y3, y4 and the
+ * step's end point are tested in that order; the first outside the block
+ * terminates the particle in that step with its position frozen at the last
+ * inside position; a non-finite velocity sample flags it INVALID likewise. */
+int bto_advect_interval(bto_ctx *ctx, const void *const *d_fields, const double *times, int32_t n_steps,
+                        int32_t dtype, int32_t flags, void *stream);
+
+/* Write the interval's flow map in seed-id order (Section 2.3: end positions
+ * saved at the end of the interval).  Per seed: d_seed_xyz (n x 3 doubles,
+ * may be NULL), d_end_xyz (n x 3 doubles, world coordinates; for terminated
+ * and invalid seeds the last inside position), d_flag (BTO_VALID /
+ * BTO_TERMINATED / BTO_INVALID), d_exit_step (step of termination, or the
+ * interval's step count for valid seeds).  If n_valid_out is non-NULL the call
+ * synchronizes `stream` and returns the number of valid seeds.  The particle
+ * state is left unchanged (more steps may follow). */
+int bto_flowmap_out(bto_ctx *ctx, double *d_seed_xyz, double *d_end_xyz, uint8_t *d_flag,
+                    int32_t *d_exit_step, int64_t *n_valid_out, void *stream);
+
+/* Counters of the current interval.  Synchronizes `stream`. */
+int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTO_H */

@@ -1,0 +1,150 @@
+"""Python face of the C-ABI: one ``Context`` per block.
+
+Argument marshalling only.  torch tensors provide device memory and the
+current HIP stream; every step of the path (seeding, RK4 advection, boundary
+termination, compaction, flow-map writing) runs in the library's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BTOError
+
+_TORCH_DT = {torch.float32: _lib.BTO_F32, torch.float16: _lib.BTO_F16, torch.bfloat16: _lib.BTO_BF16}
+_MODES = {"linear": _lib.BTO_TIME_LINEAR, "frozen": _lib.BTO_TIME_FROZEN}
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def grid_to_device(grid: np.ndarray, dtype: str, device="cuda") -> torch.Tensor:
+    """Upload a stored grid (float32, float16, or bfloat16 bits as uint16)."""
+    g = np.ascontiguousarray(grid)
+    if dtype == "bf16":
+        t = torch.from_numpy(g.view(np.int16)).view(torch.bfloat16)
+    else:
+        t = torch.from_numpy(g)
+    return t.to(device, non_blocking=False)
+
+
+class Context:
+    """One block of the decomposition: n = (nx, ny, nz) grid points."""
+
+    def __init__(self, n, max_particles: int, origin=(0.0, 0.0, 0.0), spacing=(1.0, 1.0, 1.0),
+                 device: int = 0):
+        self.L = _lib.load()
+        blk = _lib.Block()
+        blk.n[:] = [int(v) for v in n]
+        blk.origin[:] = [float(v) for v in origin]
+        blk.spacing[:] = [float(v) for v in spacing]
+        self.n = tuple(int(v) for v in n)
+        self.device = int(device)
+        self.max_particles = int(max_particles)
+        h = ctypes.c_void_p()
+        rc = self.L.bto_create(ctypes.byref(blk), int(max_particles), self.device, ctypes.byref(h))
+        if rc != 0:
+            raise BTOError(rc, "bto_create failed (bad block, capacity or device, or out of memory)")
+        self._h = h
+        self.n_seeds = 0
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, rc: int):
+        if rc != 0:
+            msg = self.L.bto_last_error(self._h).decode(errors="replace")
+            raise BTOError(rc, msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.L.bto_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    # -- the path ----------------------------------------------------------
+    def seed(self, stride: int, offset=None, stream=None) -> int:
+        off = None if offset is None else (ctypes.c_double * 3)(*[float(v) for v in offset])
+        P = ctypes.c_int64()
+        self._check(self.L.bto_seed(self._h, int(stride), off, ctypes.byref(P), _stream_ptr(stream)))
+        self.n_seeds = int(P.value)
+        return self.n_seeds
+
+    def seed_explicit(self, xyz: torch.Tensor, stream=None) -> int:
+        if xyz.dtype != torch.float64 or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+            raise ValueError("seeds must be a contiguous (n, 3) float64 device tensor")
+        self._check(self.L.bto_seed_explicit(self._h, xyz.data_ptr(), int(xyz.shape[0]), _stream_ptr(stream)))
+        self.n_seeds = int(xyz.shape[0])
+        return self.n_seeds
+
+    def advect(self, grids: Sequence[torch.Tensor], times, mode: str = "linear", stream=None):
+        """n = len(grids) - 1 RK4 steps through the given consecutive cycles."""
+        if len(grids) < 2:
+            raise ValueError("need at least two grids (one step)")
+        dt = grids[0].dtype
+        if dt not in _TORCH_DT:
+            raise ValueError(f"unsupported grid dtype {dt}")
+        shape = (self.n[2], self.n[1], self.n[0], 3)
+        for g in grids:
+            if g.dtype != dt or tuple(g.shape) != shape or not g.is_contiguous() or not g.is_cuda:
+                raise ValueError(f"every grid must be a contiguous {dt} device tensor of shape {shape}")
+        times = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        if times.shape != (len(grids),):
+            raise ValueError("one time per grid")
+        ptrs = (ctypes.c_void_p * len(grids))(*[g.data_ptr() for g in grids])
+        self._check(self.L.bto_advect_interval(self._h, ptrs, times.ctypes.data, len(grids) - 1,
+                                               _TORCH_DT[dt], _MODES[mode], _stream_ptr(stream)))
+
+    def advect_ptrs(self, ptrs, times, dtype: int, mode: str = "linear", stream=None):
+        """Same as ``advect`` with raw device pointers (no per-call tensor checks)."""
+        arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        self._check(self.L.bto_advect_interval(self._h, arr, t.ctypes.data, len(ptrs) - 1, int(dtype),
+                                               _MODES[mode], _stream_ptr(stream)))
+
+    def flowmap(self, with_seeds: bool = True, count_valid: bool = False, out=None, stream=None):
+        """Seed-ordered flow map: dict with end (P,3) f64, flag (P,) u8,
+        exit (P,) i32, optionally seed (P,3) f64 and n_valid."""
+        P = self.n_seeds
+        dev = torch.device("cuda", self.device)
+        if out is None:
+            out = dict(end=torch.empty((P, 3), dtype=torch.float64, device=dev),
+                       flag=torch.empty(P, dtype=torch.uint8, device=dev),
+                       exit=torch.empty(P, dtype=torch.int32, device=dev))
+            if with_seeds:
+                out["seed"] = torch.empty((P, 3), dtype=torch.float64, device=dev)
+        nv = ctypes.c_int64(-1)
+        self._check(self.L.bto_flowmap_out(
+            self._h, out["seed"].data_ptr() if "seed" in out else None, out["end"].data_ptr(),
+            out["flag"].data_ptr(), out["exit"].data_ptr(),
+            ctypes.byref(nv) if count_valid else None, _stream_ptr(stream)))
+        if count_valid:
+            out["n_valid"] = int(nv.value)
+        return out
+
+    def stats(self, stream=None) -> dict:
+        st = _lib.Stats()
+        self._check(self.L.bto_stats(self._h, ctypes.byref(st), _stream_ptr(stream)))
+        return dict(n_seeds=st.n_seeds, n_live=st.n_live, particle_steps=st.particle_steps,
+                    steps_done=st.steps_done)

@@ -1,0 +1,362 @@
+// C-ABI of the per-block BTO library: context, argument validation and the
+// launch sequence.  Every step of the path runs in the kernels of advect.hip
+// (and adjoint.hip); this file only owns memory and enqueues work.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bto.h"
+#include "bto_internal.h"
+
+using namespace bto;
+
+struct bto_ctx {
+    bto_block blk;
+    Geom geom;
+    int device = 0;
+    int64_t cap = 0;
+    int cus_per_xcd = 32;
+    // particle state (ping-pong)
+    PState* pos[2] = {nullptr, nullptr};
+    uint32_t* id[2] = {nullptr, nullptr};
+    int cur = 0;
+    // per-seed records
+    PState* rec_pos = nullptr;
+    int32_t* rec_meta = nullptr;
+    double* seed_xyz = nullptr;
+    // counters: ring of 3 x NSEG live counts, then the particle-step total
+    uint32_t* counts = nullptr;
+    unsigned long long* psteps = nullptr;
+    int slot = 0;           // ring slot holding the current live counts
+    // interval bookkeeping (host)
+    bool seeded = false;
+    int64_t n_seeds = 0;
+    int32_t steps_done = 0;
+    Segs segs{};
+    int64_t seg_cap[NSEG] = {0};
+    std::string err;
+};
+
+static int fail(bto_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+static int hip_fail(bto_ctx* c, hipError_t e, const char* where) {
+    return fail(c, BTO_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Pending asynchronous errors (a fault in earlier work) surface here.
+static int check_pending(bto_ctx* c) {
+    hipError_t e = hipPeekAtLastError();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return hip_fail(c, e, "earlier HIP error");
+    }
+    return BTO_OK;
+}
+
+static void set_segments(bto_ctx* c, int64_t P) {
+    for (int x = 0; x < NSEG; ++x) c->segs.base[x] = (x * P + NSEG - 1) / NSEG;
+    for (int x = 0; x < NSEG; ++x) c->seg_cap[x] = (x + 1 < NSEG ? c->segs.base[x + 1] : P) - c->segs.base[x];
+}
+
+static int blocks_per_seg(const bto_ctx* c, int64_t max_seg, int per_cu) {
+    int64_t need = (max_seg + BLOCK - 1) / BLOCK;
+    int64_t lim = (int64_t)c->cus_per_xcd * per_cu;
+    if (need < 1) need = 1;
+    return (int)(need < lim ? need : lim);
+}
+
+extern "C" {
+
+int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_ctx** out) {
+    if (!blk || !out) return BTO_EINVAL;
+    *out = nullptr;
+    for (int d = 0; d < 3; ++d) {
+        if (blk->n[d] < 2 || blk->n[d] > 1024) return BTO_EINVAL;
+        if (!(blk->spacing[d] > 0.0) || !std::isfinite(blk->spacing[d]) || !std::isfinite(blk->origin[d]))
+            return BTO_EINVAL;
+    }
+    if (max_particles < 1 || max_particles > (int64_t)0xFFFFFFFFll) return BTO_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BTO_EINVAL;
+    bto_ctx* c = new (std::nothrow) bto_ctx();
+    if (!c) return BTO_ENOMEM;
+    c->blk = *blk;
+    c->device = device;
+    c->cap = max_particles;
+    for (int d = 0; d < 3; ++d) {
+        c->geom.n[d] = blk->n[d];
+        c->geom.nmax[d] = (double)(blk->n[d] - 1);
+        c->geom.inv_sp[d] = 1.0 / blk->spacing[d];
+    }
+    c->geom.sy = (uint64_t)blk->n[0];
+    c->geom.sz = (uint64_t)blk->n[0] * (uint64_t)blk->n[1];
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return BTO_EINVAL;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount >= NSEG)
+        c->cus_per_xcd = prop.multiProcessorCount / NSEG;
+    const size_t P = (size_t)max_particles;
+    bool ok = true;
+    for (int q = 0; q < 2 && ok; ++q) {
+        ok = ok && hipMalloc(&c->pos[q], P * sizeof(PState)) == hipSuccess;
+        ok = ok && hipMalloc(&c->id[q], P * sizeof(uint32_t)) == hipSuccess;
+    }
+    ok = ok && hipMalloc(&c->rec_pos, P * sizeof(PState)) == hipSuccess;
+    ok = ok && hipMalloc(&c->rec_meta, P * sizeof(int32_t)) == hipSuccess;
+    ok = ok && hipMalloc(&c->seed_xyz, P * 3 * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&c->counts, 3 * NSEG * sizeof(uint32_t) + 64) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        bto_destroy(c);
+        return BTO_ENOMEM;
+    }
+    c->psteps = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(c->counts) + 3 * NSEG * sizeof(uint32_t) +
+                                                      32);
+    *out = c;
+    return BTO_OK;
+}
+
+int bto_destroy(bto_ctx* c) {
+    if (!c) return BTO_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (int q = 0; q < 2; ++q) {
+        if (c->pos[q]) (void)hipFree(c->pos[q]);
+        if (c->id[q]) (void)hipFree(c->id[q]);
+    }
+    if (c->rec_pos) (void)hipFree(c->rec_pos);
+    if (c->rec_meta) (void)hipFree(c->rec_meta);
+    if (c->seed_xyz) (void)hipFree(c->seed_xyz);
+    if (c->counts) (void)hipFree(c->counts);
+    delete c;
+    return BTO_OK;
+}
+
+const char* bto_last_error(const bto_ctx* c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+static int begin(bto_ctx* c) {
+    if (!c) return BTO_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, BTO_EHIP, "hipSetDevice failed");
+    return check_pending(c);
+}
+
+static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hipStream_t s) {
+    uint32_t vals[3 * NSEG] = {0};
+    for (int x = 0; x < NSEG; ++x) vals[x] = seg_counts ? seg_counts[x] : 0u;
+    hipError_t e = launch_set_counts(c->counts, vals, 3 * NSEG, c->psteps, s);
+    if (e != hipSuccess) return hip_fail(c, e, "set_counts launch");
+    c->slot = 0;
+    c->cur = 0;
+    c->seeded = true;
+    c->n_seeds = P;
+    c->steps_done = 0;
+    return BTO_OK;
+}
+
+int bto_seed(bto_ctx* c, int32_t stride, const double* offset3, int64_t* n_seeds_out, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (stride < 1) return fail(c, BTO_EINVAL, "stride must be >= 1 (got %d)", stride);
+    SeedLatticeArgs a{};
+    int64_t P = 1;
+    for (int d = 0; d < 3; ++d) {
+        const double off = offset3 ? offset3[d] : (stride - 1) / 2.0;
+        if (!std::isfinite(off) || off < 0.0) return fail(c, BTO_EINVAL, "lattice offset must be finite and >= 0");
+        a.off[d] = off;
+        a.m[d] = off > (double)(c->blk.n[d] - 1) ? 0 : (int32_t)std::floor((c->blk.n[d] - 1 - off) / stride) + 1;
+        P *= a.m[d];
+        a.origin[d] = c->blk.origin[d];
+        a.spacing[d] = c->blk.spacing[d];
+    }
+    if (P > c->cap) return fail(c, BTO_ERANGE, "lattice has %lld seeds, capacity is %lld", (long long)P,
+                                (long long)c->cap);
+    a.stride = stride;
+    a.P = P;
+    set_segments(c, P);
+    a.segs = c->segs;
+    a.pos = c->pos[0];
+    a.id = c->id[0];
+    a.seed_xyz = c->seed_xyz;
+    a.rec_meta = c->rec_meta;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t cnt[NSEG];
+    for (int x = 0; x < NSEG; ++x) cnt[x] = (uint32_t)c->seg_cap[x];
+    rc = start_interval(c, P, cnt, s);
+    if (rc) return rc;
+    if (P > 0) {
+        hipError_t e = launch_seed_lattice(a, s);
+        if (e != hipSuccess) return hip_fail(c, e, "seed launch");
+    }
+    if (n_seeds_out) *n_seeds_out = P;
+    return BTO_OK;
+}
+
+int bto_seed_explicit(bto_ctx* c, const double* d_xyz, int64_t n, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && !d_xyz)) return fail(c, BTO_EINVAL, "null seed array or negative count");
+    if (n > c->cap) return fail(c, BTO_ERANGE, "%lld seeds, capacity is %lld", (long long)n, (long long)c->cap);
+    set_segments(c, n);
+    hipStream_t s = (hipStream_t)stream;
+    rc = start_interval(c, n, nullptr, s);
+    if (rc) return rc;
+    if (n == 0) return BTO_OK;
+    SeedExplicitArgs a{};
+    a.xyz = d_xyz;
+    a.P = n;
+    a.g = c->geom;
+    a.segs = c->segs;
+    for (int d = 0; d < 3; ++d) {
+        a.origin[d] = c->blk.origin[d];
+        a.inv_sp[d] = 1.0 / c->blk.spacing[d];
+    }
+    a.pos = c->pos[0];
+    a.id = c->id[0];
+    a.count = c->counts;  // slot 0
+    a.seed_xyz = c->seed_xyz;
+    a.rec_pos = c->rec_pos;
+    a.rec_meta = c->rec_meta;
+    hipError_t e = launch_seed_explicit(a, s);
+    if (e != hipSuccess) return hip_fail(c, e, "seed_explicit launch");
+    return BTO_OK;
+}
+
+int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* times, int32_t n_steps,
+                        int32_t dtype, int32_t flags, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (!d_fields || !times) return fail(c, BTO_EINVAL, "null field or time array");
+    if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
+    if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
+    if (flags != BTO_TIME_LINEAR && flags != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    for (int32_t q = 0; q <= n_steps; ++q)
+        if (!d_fields[q]) return fail(c, BTO_EINVAL, "field pointer %d is null", q);
+    for (int32_t q = 0; q < n_steps; ++q)
+        if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
+            return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
+    if (!c->seeded) return fail(c, BTO_ESTATE, "advect called before seeding");
+    if ((int64_t)c->steps_done + n_steps >= (1 << 27)) return fail(c, BTO_ERANGE, "interval too long");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n_seeds == 0) {
+        c->steps_done += n_steps;
+        return BTO_OK;
+    }
+    int64_t max_seg = 0;
+    for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
+    const int per_cu = advect_max_blocks_per_cu(dtype, flags);
+    const int R = blocks_per_seg(c, max_seg, per_cu);
+    // launches of (nearly) equal length, at most KMAX steps each
+    const int nl = (n_steps + KMAX - 1) / KMAX;
+    for (int32_t l = 0, q0 = 0; l < nl; ++l) {
+        const int K = n_steps / nl + (l < n_steps % nl ? 1 : 0);
+        AdvectArgs a{};
+        for (int q = 0; q <= K; ++q) a.f[q] = static_cast<const char*>(d_fields[q0 + q]);
+        for (int q = 0; q < K; ++q) a.h[q] = times[q0 + q + 1] - times[q0 + q];
+        a.g = c->geom;
+        a.K = K;
+        a.step0 = c->steps_done;
+        a.segs = c->segs;
+        a.in_pos = c->pos[c->cur];
+        a.in_id = c->id[c->cur];
+        a.out_pos = c->pos[1 - c->cur];
+        a.out_id = c->id[1 - c->cur];
+        a.in_count = c->counts + NSEG * c->slot;
+        a.out_count = c->counts + NSEG * ((c->slot + 1) % 3);
+        a.clear_count = c->counts + NSEG * ((c->slot + 2) % 3);
+        a.rec_pos = c->rec_pos;
+        a.rec_meta = c->rec_meta;
+        a.psteps = c->psteps;
+        hipError_t e = launch_advect(a, dtype, flags, R, s);
+        if (e != hipSuccess) return hip_fail(c, e, "advect launch");
+        c->cur = 1 - c->cur;
+        c->slot = (c->slot + 1) % 3;
+        c->steps_done += K;
+        q0 += K;
+    }
+    return BTO_OK;
+}
+
+int bto_flowmap_out(bto_ctx* c, double* d_seed_xyz, double* d_end_xyz, uint8_t* d_flag, int32_t* d_exit_step,
+                    int64_t* n_valid_out, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (!d_end_xyz || !d_flag || !d_exit_step) return fail(c, BTO_EINVAL, "null output pointer");
+    if (!c->seeded) return fail(c, BTO_ESTATE, "flowmap_out called before seeding");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n_seeds > 0) {
+        FlowmapArgs a{};
+        a.P = c->n_seeds;
+        a.steps_done = c->steps_done;
+        a.segs = c->segs;
+        a.count = c->counts + NSEG * c->slot;
+        a.pos = c->pos[c->cur];
+        a.id = c->id[c->cur];
+        a.rec_pos = c->rec_pos;
+        a.rec_meta = c->rec_meta;
+        a.seed_xyz = c->seed_xyz;
+        for (int d = 0; d < 3; ++d) {
+            a.origin[d] = c->blk.origin[d];
+            a.spacing[d] = c->blk.spacing[d];
+        }
+        a.out_seed = d_seed_xyz;
+        a.out_end = d_end_xyz;
+        a.out_flag = d_flag;
+        a.out_exit = d_exit_step;
+        int64_t max_seg = 0;
+        for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
+        hipError_t e = launch_flowmap(a, blocks_per_seg(c, max_seg, 4), s);
+        if (e != hipSuccess) return hip_fail(c, e, "flowmap launch");
+    }
+    if (n_valid_out) {
+        bto_stats_t st;
+        rc = bto_stats(c, &st, stream);
+        if (rc) return rc;
+        *n_valid_out = st.n_live;
+    }
+    return BTO_OK;
+}
+
+int bto_stats(bto_ctx* c, bto_stats_t* out, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (!out) return fail(c, BTO_EINVAL, "null output");
+    std::memset(out, 0, sizeof *out);
+    out->n_seeds = c->n_seeds;
+    out->steps_done = c->steps_done;
+    if (!c->seeded) return BTO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t cnt[NSEG];
+    unsigned long long ps = 0;
+    hipError_t e = hipMemcpyAsync(cnt, c->counts + NSEG * c->slot, sizeof cnt, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ps, c->psteps, sizeof ps, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "stats readback");
+    int64_t live = 0;
+    for (int x = 0; x < NSEG; ++x) live += cnt[x];
+    out->n_live = live;
+    out->particle_steps = (int64_t)ps;
+    return BTO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,226 @@
+// Device-side building blocks of the BTO advection path for gfx950.
+//
+// Particle state between launches: the grid cell (10 bits per axis, packed in
+// one dword) plus the FP32 offset inside it -- one 16-byte record, loaded and
+// stored as a single dwordx4.  Inside a launch the position lives in FP64
+// registers (cell + offset is exact in FP64), so stage points and the step
+// update are formed in FP64 and the boundary test is exact; the velocity
+// sampler itself runs in FP32.
+//
+// Velocity grids stay in the caller's layout (AoS xyz per point, x fastest).
+// The sampler reads each cell as four x-rows of two adjacent points (24 bytes
+// for float32, 12 bytes for float16/bfloat16), one vector load per row; gfx950
+// under ROCm runs with unaligned global access enabled, so the 2-byte-aligned
+// 12-byte rows of 16-bit grids need no padding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bto {
+
+constexpr int KMAX = 32;   // RK4 steps fused into one launch (one per cycle)
+constexpr int NSEG = 8;    // particle segments, one per XCD
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+
+enum : int { S_VALID = 0, S_TERMINATED = 1, S_INVALID = 2 };
+enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+enum : int { MODE_LINEAR = 0, MODE_FROZEN = 1 };
+constexpr int32_t META_LIVE = -1;  // record slot of a particle still advancing
+constexpr int META_SHIFT = 28;     // meta = flag << 28 | exit step
+
+struct __align__(16) PState {
+    uint32_t cell;  // cx | cy << 10 | cz << 20
+    float f[3];     // offset inside the cell, [0, 1]
+};
+
+__device__ __forceinline__ void unpack(const PState& s, double x[3]) {
+    x[0] = (double)(s.cell & 1023u) + (double)s.f[0];
+    x[1] = (double)((s.cell >> 10) & 1023u) + (double)s.f[1];
+    x[2] = (double)((s.cell >> 20) & 1023u) + (double)s.f[2];
+}
+
+__device__ __forceinline__ PState pack(const double x[3]) {
+    PState s;
+    uint32_t c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double fl = floor(x[d]);
+        c[d] = (uint32_t)(int)fl;
+        s.f[d] = (float)(x[d] - fl);
+    }
+    s.cell = c[0] | (c[1] << 10) | (c[2] << 20);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Velocity rows: two x-adjacent grid points, 6 components.
+// ---------------------------------------------------------------------------
+struct __attribute__((packed, aligned(4))) Row32 { float v[6]; };
+struct __attribute__((packed, aligned(2))) Row16 { uint16_t v[6]; };
+
+template <int DT> struct Field;
+
+template <> struct Field<DT_F32> {
+    static constexpr int BYTES = 12;  // per grid point
+    __device__ __forceinline__ static void row(const char* base, uint64_t pt, float out[6]) {
+        const Row32 r = *reinterpret_cast<const Row32*>(base + pt * 12u);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out[q] = r.v[q];
+    }
+};
+
+template <> struct Field<DT_F16> {
+    static constexpr int BYTES = 6;
+    __device__ __forceinline__ static void row(const char* base, uint64_t pt, float out[6]) {
+        const Row16 r = *reinterpret_cast<const Row16*>(base + pt * 6u);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out[q] = (float)__builtin_bit_cast(_Float16, r.v[q]);
+    }
+};
+
+template <> struct Field<DT_BF16> {
+    static constexpr int BYTES = 6;
+    __device__ __forceinline__ static void row(const char* base, uint64_t pt, float out[6]) {
+        const Row16 r = *reinterpret_cast<const Row16*>(base + pt * 6u);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) out[q] = __uint_as_float((uint32_t)r.v[q] << 16);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Block geometry in cell units.
+// ---------------------------------------------------------------------------
+struct Geom {
+    int32_t n[3];        // grid points per axis
+    double nmax[3];      // n - 1: the closed box is [0, nmax]
+    double inv_sp[3];    // 1 / spacing: world velocity -> cells per unit time
+    uint64_t sy, sz;     // point strides of y and z
+};
+
+__device__ __forceinline__ bool inside(const Geom& g, const double p[3]) {
+    return p[0] >= 0.0 && p[0] <= g.nmax[0] && p[1] >= 0.0 && p[1] <= g.nmax[1] &&
+           p[2] >= 0.0 && p[2] <= g.nmax[2];
+}
+
+// Sampling cell i_d = min(floor(p_d), n_d - 2) and FP32 offset f_d = p_d - i_d.
+struct Cell {
+    uint64_t base;  // point index of corner (i, j, k)
+    float f[3];
+};
+
+__device__ __forceinline__ Cell locate(const Geom& g, const double p[3]) {
+    Cell c;
+    int i[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int v = (int)floor(p[d]);
+        v = v > g.n[d] - 2 ? g.n[d] - 2 : v;
+        i[d] = v;
+        c.f[d] = (float)(p[d] - (double)v);
+    }
+    c.base = (uint64_t)i[0] + g.sy * (uint64_t)i[1] + g.sz * (uint64_t)i[2];
+    return c;
+}
+
+__device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// Trilinear interpolation of 8 corner values given as 4 x-rows
+// (row r = y-offset (r & 1), z-offset (r >> 1)), component-interleaved.
+__device__ __forceinline__ void trilerp(const float R[4][6], const float f[3], float out[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float a00 = lerp(R[0][c], R[0][3 + c], f[0]);
+        const float a10 = lerp(R[1][c], R[1][3 + c], f[0]);
+        const float a01 = lerp(R[2][c], R[2][3 + c], f[0]);
+        const float a11 = lerp(R[3][c], R[3][3 + c], f[0]);
+        const float b0 = lerp(a00, a10, f[1]);
+        const float b1 = lerp(a01, a11, f[1]);
+        out[c] = lerp(b0, b1, f[2]);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void load_cell(const Geom& g, const char* V, const Cell& c, float R[4][6]) {
+    Field<DT>::row(V, c.base, R[0]);
+    Field<DT>::row(V, c.base + g.sy, R[1]);
+    Field<DT>::row(V, c.base + g.sz, R[2]);
+    Field<DT>::row(V, c.base + g.sy + g.sz, R[3]);
+}
+
+// T(V, p): one grid level.
+template <int DT>
+__device__ __forceinline__ void sample1(const Geom& g, const char* V, const double p[3], float out[3]) {
+    const Cell c = locate(g, p);
+    float R[4][6];
+    load_cell<DT>(g, V, c, R);
+    trilerp(R, c.f, out);
+}
+
+// (T(V0, p) + T(V1, p)) / 2: the midpoint in time.  Interpolation is linear in
+// the grid values, so the two levels are averaged per corner first.
+template <int DT>
+__device__ __forceinline__ void sample_mid(const Geom& g, const char* V0, const char* V1, const double p[3],
+                                           float out[3]) {
+    const Cell c = locate(g, p);
+    float R[4][6], S[4][6];
+    load_cell<DT>(g, V0, c, R);
+    load_cell<DT>(g, V1, c, S);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) R[r][q] = 0.5f * (R[r][q] + S[r][q]);
+    trilerp(R, c.f, out);
+}
+
+__device__ __forceinline__ bool finite3(const float k[3]) {
+    return __builtin_isfinite(k[0]) && __builtin_isfinite(k[1]) && __builtin_isfinite(k[2]);
+}
+
+// One classic RK4 step of one cycle: stage times t, t+h/2, t+h/2, t+h with the
+// field linear in time between V0 (cycle n) and V1 (cycle n+1), or V0 only
+// when frozen.  Each stage velocity is checked finite right after sampling;
+// each later stage point and the end point are checked inside the block, in
+// order.  On any event x is left at the step's start.
+template <int DT, int MODE>
+__device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, double x[3]) {
+    const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
+    float k1[3], k2[3], k3[3], k4[3];
+    double y[3];
+
+    sample1<DT>(g, V0, x, k1);
+    if (!finite3(k1)) return S_INVALID;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) y[d] = fma(0.5 * hs[d], (double)k1[d], x[d]);
+    if (!inside(g, y)) return S_TERMINATED;
+
+    if (MODE == MODE_LINEAR) sample_mid<DT>(g, V0, V1, y, k2);
+    else sample1<DT>(g, V0, y, k2);
+    if (!finite3(k2)) return S_INVALID;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) y[d] = fma(0.5 * hs[d], (double)k2[d], x[d]);
+    if (!inside(g, y)) return S_TERMINATED;
+
+    if (MODE == MODE_LINEAR) sample_mid<DT>(g, V0, V1, y, k3);
+    else sample1<DT>(g, V0, y, k3);
+    if (!finite3(k3)) return S_INVALID;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) y[d] = fma(hs[d], (double)k3[d], x[d]);
+    if (!inside(g, y)) return S_TERMINATED;
+
+    sample1<DT>(g, MODE == MODE_LINEAR ? V1 : V0, y, k4);
+    if (!finite3(k4)) return S_INVALID;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float ks = (k1[d] + k4[d]) + 2.0f * (k2[d] + k3[d]);
+        y[d] = fma(hs[d] * (1.0 / 6.0), (double)ks, x[d]);
+    }
+    if (!inside(g, y)) return S_TERMINATED;
+    x[0] = y[0];
+    x[1] = y[1];
+    x[2] = y[2];
+    return S_VALID;
+}
+
+}  // namespace bto

@@ -1,0 +1,90 @@
+// Host <-> kernel interface of the BTO library (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bto_device.h"
+
+namespace bto {
+
+// Live particles are split into NSEG contiguous segments of the ping-pong
+// buffers.  Workgroup b of a launch works on segment b % NSEG: consecutive
+// workgroups are dispatched round-robin over the 8 XCDs, so each XCD keeps
+// one spatially compact slab of particles (and of the field) in its own L2.
+struct Segs {
+    int64_t base[NSEG];  // first slot of each segment
+};
+
+struct AdvectArgs {
+    const char* f[KMAX + 1];  // grids of cycles c0 .. c0 + K
+    double h[KMAX];           // step sizes
+    Geom g;
+    int32_t K;                // steps in this launch
+    int32_t step0;            // steps already done in the interval
+    Segs segs;
+    const PState* in_pos;
+    const uint32_t* in_id;
+    PState* out_pos;
+    uint32_t* out_id;
+    const uint32_t* in_count;   // NSEG live counts entering the launch
+    uint32_t* out_count;        // NSEG counts of survivors (zero on entry)
+    uint32_t* clear_count;      // NSEG counts cleared for the launch after next
+    PState* rec_pos;            // per seed id: final state of ended particles
+    int32_t* rec_meta;          // per seed id: flag << 28 | exit step
+    unsigned long long* psteps; // attempted particle-steps
+};
+
+struct SeedLatticeArgs {
+    int32_t m[3];        // lattice points per axis
+    double off[3];       // lattice offset (cells)
+    int32_t stride;
+    int64_t P;
+    Segs segs;
+    double origin[3], spacing[3];
+    PState* pos;
+    uint32_t* id;
+    double* seed_xyz;    // per seed id, world coordinates
+    int32_t* rec_meta;
+};
+
+struct SeedExplicitArgs {
+    const double* xyz;   // world
+    int64_t P;
+    Geom g;
+    Segs segs;
+    double origin[3], inv_sp[3];
+    PState* pos;
+    uint32_t* id;
+    uint32_t* count;     // NSEG, zero on entry
+    double* seed_xyz;
+    PState* rec_pos;
+    int32_t* rec_meta;
+};
+
+struct FlowmapArgs {
+    int64_t P;
+    int32_t steps_done;
+    Segs segs;
+    const uint32_t* count;
+    const PState* pos;
+    const uint32_t* id;
+    const PState* rec_pos;
+    const int32_t* rec_meta;
+    const double* seed_xyz;
+    double origin[3], spacing[3];
+    double* out_seed;    // may be null
+    double* out_end;
+    uint8_t* out_flag;
+    int32_t* out_exit;
+};
+
+hipError_t launch_seed_lattice(const SeedLatticeArgs& a, hipStream_t s);
+hipError_t launch_seed_explicit(const SeedExplicitArgs& a, hipStream_t s);
+hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, unsigned long long* psteps,
+                             hipStream_t s);
+hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int blocks_per_seg, hipStream_t s);
+hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t s);
+int advect_max_blocks_per_cu(int dtype, int mode);
+
+}  // namespace bto

@@ -1,0 +1,74 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C-ABI
+and the oracle on the same seeded inputs, and compare them."""
+
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+# Tolerances (cells): termination flags and exit steps must match exactly for
+# every particle whose oracle decision points all stay at least MARGIN from a
+# face; end positions within POS_TOL for FP32 arithmetic on the stored grid.
+MARGIN = 1e-6
+POS_TOL = 1e-5
+
+
+def run_gpu(n, grids_dev, times, stride=None, seeds=None, mode="linear", chunks=None, origin=(0, 0, 0),
+            spacing=(1, 1, 1), cap=None):
+    """Seed, advect (optionally in several calls), write the flow map; returns
+    numpy arrays in seed order plus the counters."""
+    import torch
+    from paper_2004_02003_amd import Context
+
+    N = len(grids_dev) - 1
+    if cap is None:
+        cap = len(seeds) if seeds is not None else int(np.prod([(nd - 1 - (stride - 1) / 2) // stride + 1
+                                                                for nd in n]))
+    ctx = Context(n, max(int(cap), 1), origin=origin, spacing=spacing)
+    try:
+        if seeds is not None:
+            ctx.seed_explicit(torch.as_tensor(np.ascontiguousarray(seeds, dtype=np.float64), device="cuda"))
+        else:
+            ctx.seed(stride)
+        if chunks is None:
+            chunks = [N]
+        q = 0
+        for k in chunks:
+            ctx.advect(grids_dev[q:q + k + 1], times[q:q + k + 1], mode=mode)
+            q += k
+        assert q == N
+        fm = ctx.flowmap(count_valid=True)
+        st = ctx.stats()
+        torch.cuda.synchronize()
+        out = {k: v.cpu().numpy() for k, v in fm.items() if k != "n_valid"}
+        out["n_valid"] = fm["n_valid"]
+        out["stats"] = st
+        return out
+    finally:
+        ctx.close()
+
+
+def compare(g, o, pos_tol=POS_TOL, margin=MARGIN, per_particle_tol=None, label=""):
+    """Assert parity of a GPU flow map ``g`` with an oracle result ``o``."""
+    amb = o["margin"] < margin
+    ok = ~amb
+    bad_flag = np.nonzero(ok & (g["flag"] != o["flag"]))[0]
+    assert bad_flag.size == 0, f"{label}: flag mismatch at {bad_flag[:10]} (of {ok.sum()})"
+    bad_exit = np.nonzero(ok & (g["exit"] != o["exit"]))[0]
+    assert bad_exit.size == 0, f"{label}: exit-step mismatch at {bad_exit[:10]}"
+    err = np.abs(g["end"] - o["end"]).max(axis=1)
+    tol = pos_tol if per_particle_tol is None else np.maximum(pos_tol, per_particle_tol)
+    bad = np.nonzero(ok & (err > tol))[0]
+    assert bad.size == 0, (f"{label}: end position error {err[bad[:5]]} > tol at {bad[:5]}; "
+                           f"max err {err[ok].max():.3e}")
+    return dict(n=len(err), ambiguous=int(amb.sum()), max_err=float(err[ok].max()) if ok.any() else 0.0,
+                mean_err=float(err[ok].mean()) if ok.any() else 0.0,
+                terminated=float((o["flag"] == oracle.TERMINATED).mean()))
+
+
+def oracle_lattice(field, times, n, stride, N, mode=oracle.LINEAR, ids=None, jac=False, nthreads=0):
+    seeds = oracle.seed_lattice(n, stride)
+    if ids is not None:
+        seeds = seeds[ids]
+    return seeds, oracle.flowmap(field, times, seeds, N, mode=mode, jac=jac, nthreads=nthreads)

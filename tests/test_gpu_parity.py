@@ -1,0 +1,221 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Flags and exit steps must match exactly outside a 1e-6-cell face margin; end
+positions within 1e-5 cells (FP32 arithmetic on the stored grid; FP64
+positions).  Inputs are seeded synthetic fields; every expected value comes
+from the oracle run on the very same stored grid values.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from bto_inputs import fields, quant
+from bto_inputs.workloads import WORKLOADS
+
+from .parity import compare, oracle_lattice, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2004_02003_amd import _lib
+
+    _lib.load()  # fails loudly if the library is missing
+
+
+def _dev(grids, dtype):
+    from paper_2004_02003_amd import grid_to_device
+
+    return [grid_to_device(g, dtype) for g in grids]
+
+
+def test_seeding_without_steps_returns_the_seeds():
+    _say("seed-only 37x23x19 stride 3")
+    n = (37, 23, 19)
+    import torch
+    from paper_2004_02003_amd import Context
+
+    with Context(n, 5000) as ctx:
+        P = ctx.seed(3)
+        fm = ctx.flowmap(count_valid=True)
+        torch.cuda.synchronize()
+    seeds = oracle.seed_lattice(n, 3)
+    assert P == len(seeds) and fm["n_valid"] == P
+    assert np.array_equal(fm["seed"].cpu().numpy(), seeds)
+    assert np.array_equal(fm["end"].cpu().numpy(), seeds)
+    assert np.all(fm["flag"].cpu().numpy() == 0) and np.all(fm["exit"].cpu().numpy() == 0)
+
+
+def test_uniform_flow_closed_form_on_gpu():
+    _say("uniform flow 20^3 non-uniform steps")
+    rng = np.random.default_rng(7)
+    n = (20, 20, 20)
+    N = 30
+    times = np.concatenate([[0.25], 0.25 + np.cumsum(rng.uniform(0.1, 0.5, N))])
+    u = np.array([0.7, -0.3, 0.45])
+    s = fields.uniform_flow(n, u, times)
+    g = run_gpu(n, _dev(s.grids("f32"), "f32"), times, stride=3)
+    o = oracle.flowmap(oracle.Field(n, s.grids("f32")), times, oracle.seed_lattice(n, 3), N)
+    compare(g, o, label="uniform")
+    assert g["stats"]["particle_steps"] == int(np.where(o["flag"] == 0, N, o["exit"] + 1).sum())
+
+
+def test_solid_body_rotation_on_gpu():
+    _say("solid-body rotation 16x16x6")
+    n = (16, 16, 6)
+    N = 40
+    times = np.arange(N + 1) * 0.125
+    s = fields.solid_body_rotation(n, 0.5, (7.5, 7.5), 0.05, times)
+    rng = np.random.default_rng(2)
+    r0 = rng.uniform(0.5, 6.0, 300)
+    ph = rng.uniform(0, 2 * math.pi, 300)
+    seeds = np.stack([7.5 + r0 * np.cos(ph), 7.5 + r0 * np.sin(ph), np.full(300, 1.5)], axis=1)
+    g = run_gpu(n, _dev(s.grids("f32"), "f32"), times, seeds=seeds)
+    th = 0.5 * 0.125
+    R = 1 + 1j * th + (1j * th) ** 2 / 2 + (1j * th) ** 3 / 6 + (1j * th) ** 4 / 24
+    zN = ((seeds[:, 0] - 7.5) + 1j * (seeds[:, 1] - 7.5)) * R ** N
+    assert np.all(g["flag"] == 0)
+    np.testing.assert_allclose(g["end"][:, 0], 7.5 + zN.real, atol=1e-5)
+    np.testing.assert_allclose(g["end"][:, 1], 7.5 + zN.imag, atol=1e-5)
+
+
+def test_double_gyre_full_parity():
+    wl = WORKLOADS["double_gyre_32"]
+    _say(f"{wl.name} full")
+    s = wl.make_field()
+    gr = s.grids("f32")
+    g = run_gpu(wl.n, _dev(gr, "f32"), s.times, stride=wl.stride)
+    _, o = oracle_lattice(oracle.Field(wl.n, gr), s.times, wl.n, wl.stride, wl.n_steps)
+    res = compare(g, o, label=wl.name)
+    assert 0.15 < res["terminated"] < 0.35
+    assert g["n_valid"] == int((o["flag"] == 0).sum()) or res["ambiguous"] > 0
+
+
+def test_double_gyre_frozen_mode_parity():
+    wl = WORKLOADS["double_gyre_32"]
+    _say(f"{wl.name} frozen")
+    s = wl.make_field()
+    gr = s.grids("f32")
+    g = run_gpu(wl.n, _dev(gr, "f32"), s.times, stride=wl.stride, mode="frozen")
+    _, o = oracle_lattice(oracle.Field(wl.n, gr), s.times, wl.n, wl.stride, wl.n_steps, mode=oracle.FROZEN)
+    compare(g, o, label="frozen")
+
+
+def test_streaming_one_call_per_cycle_matches_one_call():
+    wl = WORKLOADS["double_gyre_32"]
+    _say("double gyre streaming (2 grids per call)")
+    s = wl.make_field()
+    gr = s.grids("f32")
+    dev = _dev(gr, "f32")
+    a = run_gpu(wl.n, dev, s.times, stride=2)
+    b = run_gpu(wl.n, dev, s.times, stride=2, chunks=[1] * wl.n_steps)
+    c = run_gpu(wl.n, dev, s.times, stride=2, chunks=[7, 33, 10])
+    _, o = oracle_lattice(oracle.Field(wl.n, gr), s.times, wl.n, 2, wl.n_steps)
+    for r, lab in ((b, "per-cycle"), (c, "ragged chunks")):
+        compare(r, o, label=lab)
+        amb = o["margin"] < 1e-6
+        assert np.array_equal(r["flag"][~amb], a["flag"][~amb])
+        # each launch re-rounds the in-cell offset to FP32 (<= 2^-25 per launch)
+        assert np.abs(r["end"] - a["end"]).max() < 5e-6
+
+
+def test_ragged_block_and_lattice_all_dtypes():
+    n = (37, 23, 19)
+    N = 12
+    s = fields.abc_noise(n, N + 1, 0.1, sigma=0.05, seed=12, global_n=48)
+    for dt in ("f32", "f16", "bf16"):
+        _say(f"ragged 37x23x19 stride 3 {dt}")
+        gr = s.grids(dt)
+        g = run_gpu(n, _dev(gr, dt), s.times, stride=3)
+        _, o = oracle_lattice(oracle.Field(n, gr, dtype=dt), s.times, n, 3, N)
+        res = compare(g, o, label=dt)
+        assert 0.0 < res["terminated"] < 1.0
+
+
+def test_explicit_seeds_including_outside_and_permutation():
+    n = (24, 24, 24)
+    N = 16
+    s = fields.abc_noise(n, N + 1, 0.05, sigma=0.02, seed=9, global_n=64)
+    gr = s.grids("f32")
+    rng = np.random.default_rng(5)
+    seeds = rng.uniform(-1.0, 24.0, size=(3000, 3))
+    seeds[:10] = [[0, 0, 0], [23, 23, 23], [23, 0, 11.5], [-1e-9, 3, 3], [3, 23.0000001, 3],
+                  [11.5, 11.5, 11.5], [0.5, 0.5, 0.5], [22.5, 22.5, 22.5], [5, 5, 23], [23, 5, 5]]
+    _say("explicit seeds 3000 (with outside)")
+    g = run_gpu(n, _dev(gr, "f32"), s.times, seeds=seeds)
+    o = oracle.flowmap(oracle.Field(n, gr), s.times, seeds, N)
+    compare(g, o, label="explicit")
+    outside = ~np.all((seeds >= 0) & (seeds <= 23), axis=1)
+    assert np.all(g["flag"][outside] == 1) and np.all(g["exit"][outside] == 0)
+    assert np.array_equal(g["end"][outside], seeds[outside])
+    perm = rng.permutation(len(seeds))
+    _say("explicit seeds permuted")
+    gp = run_gpu(n, _dev(gr, "f32"), s.times, seeds=seeds[perm])
+    assert np.array_equal(gp["flag"], g["flag"][perm])
+    assert np.array_equal(gp["exit"], g["exit"][perm])
+    assert np.array_equal(gp["end"], g["end"][perm])
+
+
+def test_world_coordinates_origin_and_spacing():
+    n = (20, 16, 12)
+    N = 10
+    s = fields.abc_noise(n, N + 1, 0.05, sigma=0.02, seed=10, global_n=40)
+    gr = s.grids("f32")
+    origin = np.array([-3.0, 10.5, 2.25])
+    spacing = np.array([0.5, 2.0, 0.25])
+    # a grid in world units per time: cell velocity times spacing
+    grw = [(quant.promote(g, "f32") * spacing).astype(np.float32) for g in gr]
+    _say("origin/spacing 20x16x12")
+    g = run_gpu(n, _dev(grw, "f32"), s.times, stride=2, origin=origin, spacing=spacing)
+    cells = [(quant.promote(g2, "f32") / spacing) for g2 in grw]
+    _, o = oracle_lattice(oracle.Field(n, cells), s.times, n, 2, N)
+    g_cells = dict(g)
+    g_cells["end"] = (g["end"] - origin) / spacing
+    compare(g_cells, o, label="world")
+    np.testing.assert_allclose((g["seed"] - origin) / spacing, oracle.seed_lattice(n, 2), atol=0)
+
+
+def test_nonfinite_velocity_flags_invalid_on_gpu():
+    n = (10, 10, 10)
+    s = fields.uniform_flow(n, [0.5, 0.0, 0.0], np.arange(6) * 0.2)
+    gs = s.grids("f32")
+    gs[2][5, 5, 5] = np.nan
+    seeds = np.array([[4.0, 5.0, 5.0], [4.0, 2.0, 2.0]])
+    _say("nan field")
+    g = run_gpu(n, _dev(gs, "f32"), s.times, seeds=seeds)
+    assert g["flag"].tolist() == [2, 0] and g["exit"][0] == 1
+    assert np.all(np.isfinite(g["end"]))
+    np.testing.assert_allclose(g["end"][0], [4.1, 5.0, 5.0], atol=1e-6)
+
+
+def test_abc_128_full_size_sampled_parity():
+    wl = WORKLOADS["abc_128"]
+    _say(f"{wl.name} full size, oracle on every 5th seed")
+    s = wl.make_field()
+    gr = s.grids("f32")
+    g = run_gpu(wl.n, _dev(gr, "f32"), s.times, stride=wl.stride)
+    ids = np.arange(0, wl.n_seeds, 5)
+    _, o = oracle_lattice(oracle.Field(wl.n, gr), s.times, wl.n, wl.stride, wl.n_steps, ids=ids)
+    sub = {k: g[k][ids] for k in ("end", "flag", "exit")}
+    res = compare(sub, o, label=wl.name)
+    _say(f"{wl.name}: {res}")
+    assert 0.08 < res["terminated"] < 0.25
+    # whole-population properties: every seed accounted for, counts consistent
+    assert g["n_valid"] == int((g["flag"] == 0).sum())
+    assert g["stats"]["n_live"] == g["n_valid"]
+    assert np.all(g["exit"][g["flag"] == 0] == wl.n_steps)
+    steps = np.where(g["flag"] == 0, wl.n_steps, g["exit"] + 1).sum()
+    assert g["stats"]["particle_steps"] == steps
