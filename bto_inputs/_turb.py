@@ -11,16 +11,25 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "turb.c")
 _LIB = os.path.join(_HERE, "libbto_inputs.so")
+_DEV_SRC = os.path.join(_HERE, "turb_dev.hip")
+_DEV_LIB = os.path.join(_HERE, "libbto_inputs_dev.so")
 _DT_CODE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 
 
 def build(force: bool = True) -> str:
-    """Compile turb.c into libbto_inputs.so next to it."""
+    """Compile turb.c (host) and turb_dev.hip (gfx950) next to them."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
+    if force or not os.path.exists(_DEV_LIB):
+        arch = os.environ.get("BTO_OFFLOAD_ARCH", "gfx950")
+        cmd = ["hipcc", f"--offload-arch={arch}", "-O3", "-ffp-contract=off", "-fPIC", "-shared",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-o", _DEV_LIB + ".tmp", _DEV_SRC]
+        subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+        os.replace(_DEV_LIB + ".tmp", _DEV_LIB)
     return _LIB
 
 
@@ -101,6 +110,50 @@ class TurbEvaluator:
 
     def fetch_user(self, dtype: str) -> int:
         return ctypes.addressof(self.tables(dtype))
+
+
+_dev_lib = None
+
+
+def dev_lib():
+    global _dev_lib
+    if _dev_lib is None:
+        if not os.path.exists(_DEV_LIB):
+            raise ImportError(f"{_DEV_LIB} missing: run bto_inputs._turb.build()")
+        L = ctypes.CDLL(_DEV_LIB)
+        L.turb_grid_dev.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_void_p] * 9 + \
+            [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+        L.turb_grid_dev.restype = ctypes.c_int
+        _dev_lib = L
+    return _dev_lib
+
+
+class DeviceTurbulence:
+    """The same series generated on the GPU (tables uploaded once); grids are
+    bit-identical to the host evaluator's."""
+
+    def __init__(self, ev: TurbEvaluator, device="cuda"):
+        import torch
+
+        self.ev = ev
+        self.t = {k: torch.as_tensor(v, device=device) for k, v in ev.arrs.items()}
+
+    def fill(self, c: int, dtype: str, out, stream=None):
+        """Write cycle ``c``'s grid into the device tensor ``out``
+        (float32 / float16 / bfloat16 / float64, shape (nz, ny, nx, 3))."""
+        import torch
+
+        code = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}[dtype]
+        nx, ny, nz = self.ev.n
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        t = self.t
+        rc = dev_lib().turb_grid_dev(nx, ny, nz, self.ev.M, t["exr"].data_ptr(), t["exi"].data_ptr(),
+                                     t["eyr"].data_ptr(), t["eyi"].data_ptr(), t["ezr"].data_ptr(),
+                                     t["ezi"].data_ptr(), t["pr"].data_ptr(), t["pi"].data_ptr(),
+                                     t["amp"].data_ptr(), int(c), code, out.data_ptr(), st)
+        if rc != 0:
+            raise RuntimeError(f"turb_grid_dev failed ({rc})")
+        return out
 
 
 def store_round(x: np.ndarray, dtype: str) -> np.ndarray:

@@ -129,6 +129,39 @@ int bto_flowmap_out(bto_ctx *ctx, double *d_seed_xyz, double *d_end_xyz, uint8_t
 /* Counters of the current interval.  Synchronizes `stream`. */
 int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
 
+/* Discrete adjoint of the interval (gradients for the north-star
+ * differentiation workload; FTLE use of the flow map: Results section).
+ * For the seeds of the current interval (bto_seed*), recompute the RK4
+ * advection through d_fields / times (same meaning as bto_advect_interval,
+ * all n_steps + 1 grids resident), storing each particle's position every
+ * ckpt_every steps, then sweep back segment by segment: recompute the
+ * segment's steps from its checkpoint and apply the transposed stage
+ * recurrences of RK4 with the trilinear sampler's gradient on the cell chosen
+ * by the floor/clamp rule.
+ *   d_cot_end  (n_seeds x n_cot x 3 floats, world units): cotangents of the
+ *              end positions; n_cot = 1 (a scalar loss L = sum c . x_end) or
+ *              3 (one per axis: d_grad_seed then holds the 3x3 flow-map
+ *              Jacobian dx_end/dx_0 per seed, row-major).
+ *   d_grad_seed (n_seeds x n_cot x 3 floats): d L / d x_0 per cotangent.
+ *   d_grad_fields: NULL, or a HOST array of n_steps + 1 device pointers to
+ *              float32 grids shaped like the velocity grids; d L / d V_c is
+ *              ADDED to them (FP32 atomics, summation order not
+ *              deterministic).  Only with n_cot = 1.
+ *   d_status (n_seeds bytes, may be NULL): BTO_VALID / BTO_TERMINATED /
+ *              BTO_INVALID from the recomputed forward.
+ * Seeds that do not stay inside the block for the whole interval contribute
+ * nothing: their gradient rows are zero.  Scratch of about
+ * n_seeds * (n_steps / ckpt_every + ckpt_every) * 24 bytes is held by the
+ * context.  The call waits for its small host-to-device tables to be copied
+ * (it synchronizes `stream` once before the launch). */
+int bto_adjoint_interval(bto_ctx *ctx, const void *const *d_fields, const double *times, int32_t n_steps,
+                         int32_t dtype, int32_t flags, const float *d_cot_end, int32_t n_cot, float *d_grad_seed,
+                         float *const *d_grad_fields, uint8_t *d_status, int32_t ckpt_every, void *stream);
+
+/* Finite-time Lyapunov exponent per seed from row-major 3x3 Jacobians:
+ * sigma = ln sqrt(lambda_max(J^T J)) / |T| (d_jac: n x 9 floats, d_out: n floats). */
+int bto_ftle(bto_ctx *ctx, const float *d_jac, int64_t n, double T, float *d_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ def __getattr__(name):
     if name in ("Context", "grid_to_device"):
         from . import context
         return getattr(context, name)
-    if name in ("BTOAdvectFn", "advect_autograd", "ftle"):
+    if name in ("BTOAdvectFn", "advect_autograd", "jacobian_ftle"):
         from . import autograd
         return getattr(autograd, name)
     raise AttributeError(name)

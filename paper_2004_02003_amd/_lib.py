@@ -19,7 +19,7 @@ BTO_VALID, BTO_TERMINATED, BTO_INVALID = 0, 1, 2
 
 EXPORTED = [
     "bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
-    "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval",
+    "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle",
 ]
 
 _ERRNAMES = {BTO_EINVAL: "BTO_EINVAL", BTO_ENOMEM: "BTO_ENOMEM", BTO_EHIP: "BTO_EHIP",
@@ -65,10 +65,10 @@ def load() -> ctypes.CDLL:
     L.bto_advect_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp]
     L.bto_flowmap_out.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
     L.bto_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
-    if hasattr(L, "bto_adjoint_interval"):
-        L.bto_adjoint_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
+    L.bto_adjoint_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
+    L.bto_ftle.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]
     for fn in EXPORTED:
-        if hasattr(L, fn):
-            getattr(L, fn).restype = getattr(L, fn).restype if fn == "bto_last_error" else ctypes.c_int
+        if fn != "bto_last_error":
+            getattr(L, fn).restype = ctypes.c_int
     _lib = L
     return L

@@ -143,6 +143,49 @@ class Context:
             out["n_valid"] = int(nv.value)
         return out
 
+    def adjoint(self, grids: Sequence[torch.Tensor], times, cot: torch.Tensor, grad_grids=None,
+                ckpt_every: int = 10, mode: str = "linear", status: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+        """Gradients d(cot . x_end)/d x_0 for the current seeds (n_cot = cot.shape[1]
+        cotangent vectors per seed; 3 unit cotangents give the Jacobian rows).
+        ``grad_grids`` (optional list of float32 tensors shaped like the grids)
+        receive d L / d V added in place."""
+        P = self.n_seeds
+        dt = grids[0].dtype
+        if cot.dim() == 2:
+            cot = cot.view(P, 1, 3)
+        if cot.dtype != torch.float32 or tuple(cot.shape[::2]) != (P, 3) or not cot.is_contiguous():
+            raise ValueError("cot must be a contiguous float32 tensor (P, n_cot, 3)")
+        ncot = int(cot.shape[1])
+        shape = (self.n[2], self.n[1], self.n[0], 3)
+        for g in grids:
+            if g.dtype != dt or tuple(g.shape) != shape or not g.is_contiguous():
+                raise ValueError("grids must share dtype and shape")
+        times = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        out = torch.empty((P, ncot, 3), dtype=torch.float32, device=cot.device)
+        ptrs = (ctypes.c_void_p * len(grids))(*[g.data_ptr() for g in grids])
+        gptr = None
+        if grad_grids is not None:
+            for g in grad_grids:
+                if g.dtype != torch.float32 or tuple(g.shape) != shape or not g.is_contiguous():
+                    raise ValueError("grad grids must be contiguous float32 tensors shaped like the grids")
+            gptr = (ctypes.c_void_p * len(grad_grids))(*[g.data_ptr() for g in grad_grids])
+        self._check(self.L.bto_adjoint_interval(
+            self._h, ptrs, times.ctypes.data, len(grids) - 1, _TORCH_DT[dt], _MODES[mode], cot.data_ptr(), ncot,
+            out.data_ptr(), gptr, status.data_ptr() if status is not None else None, int(ckpt_every),
+            _stream_ptr(stream)))
+        return out
+
+    def ftle(self, jac: torch.Tensor, T: float, stream=None) -> torch.Tensor:
+        """FTLE per seed from (P, 3, 3) float32 Jacobians."""
+        jac = jac.contiguous()
+        if jac.dtype != torch.float32 or jac.shape[1:] != (3, 3):
+            raise ValueError("jac must be float32 (P, 3, 3)")
+        out = torch.empty(jac.shape[0], dtype=torch.float32, device=jac.device)
+        self._check(self.L.bto_ftle(self._h, jac.data_ptr(), int(jac.shape[0]), float(T), out.data_ptr(),
+                                    _stream_ptr(stream)))
+        return out
+
     def stats(self, stream=None) -> dict:
         st = _lib.Stats()
         self._check(self.L.bto_stats(self._h, ctypes.byref(st), _stream_ptr(stream)))

@@ -1,0 +1,277 @@
+// Discrete adjoint of the per-block RK4 advection (gradients of end positions
+// with respect to seed positions and velocity grids), with checkpointing, and
+// the FTLE of flow-map Jacobians.
+//
+// One lane per seed.  Forward: the same RK4 stepping as the advection kernel,
+// storing the FP64 position every `k` steps (checkpoints).  Backward: for each
+// k-step segment in reverse, recompute its steps from the checkpoint (storing
+// each step's start), then walk them backwards: recompute the four stage
+// points with the sampler gradients G_s (on the cell chosen by the floor/clamp
+// rule) and apply the transposed stage recurrences to every cotangent vector.
+// Grid gradients are scattered with FP32 atomics (their summation order is
+// not deterministic).  Terminated and invalid seeds contribute nothing (the
+// loss covers only the basis flows that stay inside the block).
+#include "bto_internal.h"
+
+namespace bto {
+
+struct StageRec {
+    uint64_t base[4];
+    float f[4][3];
+    float G[4][3][3];  // d k~_r / d y_d in cells (k~ = velocity in cells per unit time)
+};
+
+// One RK4 step that also records every stage's cell, offsets and sampler
+// gradient.  Mirrors rk4_step (same operations in the same order for the
+// position), returning the same status.
+template <int DT, int MODE>
+__device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const char* V1, double h, Stepper& st,
+                                            StageRec& rec) {
+    const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
+    float k[4][3];
+    double y[3] = {st.x[0], st.x[1], st.x[2]};
+    const double coef[3] = {0.5, 0.5, 1.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        if (s > 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) y[d] = fma(coef[s - 1] * hs[d], (double)k[s - 1][d], st.x[d]);
+            if (!inside(g, y)) return S_TERMINATED;
+        }
+        const Cell c = locate(g, y);
+        rec.base[s] = c.base;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rec.f[s][d] = c.f[d];
+        float G[3][3];
+        if (MODE == MODE_FROZEN) {
+            ensure<DT>(g, V0, c.base, st.A);
+            trilerp_grad<false>(st.A.R, st.A.R, c.f, k[s], G);
+        } else if (s == 0) {
+            ensure<DT>(g, V0, c.base, st.A);
+            trilerp_grad<false>(st.A.R, st.A.R, c.f, k[s], G);
+        } else if (s == 3) {
+            ensure<DT>(g, V1, c.base, st.B);
+            trilerp_grad<false>(st.B.R, st.B.R, c.f, k[s], G);
+        } else {
+            ensure<DT>(g, V0, c.base, st.A);
+            ensure<DT>(g, V1, c.base, st.B);
+            trilerp_grad<true>(st.A.R, st.B.R, c.f, k[s], G);
+        }
+        if (!finite3(k[s])) return S_INVALID;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) rec.G[s][r][d] = (float)g.inv_sp[r] * G[r][d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float ks = (k[0][d] + k[3][d]) + 2.0f * (k[1][d] + k[2][d]);
+        y[d] = fma(hs[d] * (1.0 / 6.0), (double)ks, st.x[d]);
+    }
+    if (!inside(g, y)) return S_TERMINATED;
+    st.x[0] = y[0];
+    st.x[1] = y[1];
+    st.x[2] = y[2];
+    return S_VALID;
+}
+
+__device__ __forceinline__ void gT(const float G[3][3], const float v[3], float out[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[d] = G[0][d] * v[0] + G[1][d] * v[1] + G[2][d] * v[2];
+}
+
+// scatter coef * w_corner(f) * inv_sp_r * lam_r into grid `gf` at the cell
+__device__ __forceinline__ void scatter_cell(const Geom& g, float* gf, uint64_t base, const float f[3], float coef,
+                                             const float lam[3]) {
+    if (!gf) return;
+    const float wx[2] = {1.f - f[0], f[0]}, wy[2] = {1.f - f[1], f[1]}, wz[2] = {1.f - f[2], f[2]};
+    const float l[3] = {(float)g.inv_sp[0] * lam[0] * coef, (float)g.inv_sp[1] * lam[1] * coef,
+                        (float)g.inv_sp[2] * lam[2] * coef};
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float w = wx[a] * wy[b] * wz[c];
+                float* p = gf + 3 * (base + (uint64_t)a + g.sy * (uint64_t)b + g.sz * (uint64_t)c);
+                unsafeAtomicAdd(p + 0, w * l[0]);
+                unsafeAtomicAdd(p + 1, w * l[1]);
+                unsafeAtomicAdd(p + 2, w * l[2]);
+            }
+}
+
+template <int DT, int MODE, int NCOT>
+__global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= a.P) return;
+    const int N = a.N, K = a.k;
+    const int nseg = (N + K - 1) / K;
+    double* ck = a.ckpt + (size_t)p * 3 * (nseg > 0 ? nseg : 1);
+    double* buf = a.buf + (size_t)p * 3 * K;
+
+    Stepper st;
+    stepper_init(st);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) st.x[d] = (a.seed_xyz[3 * p + d] - a.origin[d]) * a.g.inv_sp[d];
+    int status = inside(a.g, st.x) ? S_VALID : S_TERMINATED;
+    for (int n = 0; n < N && status == S_VALID; ++n) {
+        if (n % K == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ck[3 * (n / K) + d] = st.x[d];
+        }
+        status = rk4_step<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], st);
+        if (status == S_VALID) stepper_next_cycle<MODE>(st);
+    }
+    if (a.status_out) a.status_out[p] = (uint8_t)status;
+
+    float lam[NCOT][3];
+#pragma unroll
+    for (int c = 0; c < NCOT; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            lam[c][d] = status == S_VALID ? a.cot[(p * NCOT + c) * 3 + d] * (float)a.sp[d] : 0.f;
+
+    if (status == S_VALID) {
+        for (int sg = nseg - 1; sg >= 0; --sg) {
+            const int n0 = sg * K;
+            const int n1 = (n0 + K < N) ? n0 + K : N;
+            stepper_init(st);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) st.x[d] = ck[3 * sg + d];
+            for (int n = n0; n < n1; ++n) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) buf[3 * (n - n0) + d] = st.x[d];
+                if (n + 1 < n1) {
+                    rk4_step<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], st);
+                    stepper_next_cycle<MODE>(st);
+                }
+            }
+            for (int n = n1 - 1; n >= n0; --n) {
+                Stepper sr;
+                stepper_init(sr);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sr.x[d] = buf[3 * (n - n0) + d];
+                StageRec rec;
+                rk4_step_rec<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], sr, rec);
+                const float h = (float)a.h[n];
+#pragma unroll
+                for (int c = 0; c < NCOT; ++c) {
+                    float lk[4][3], ly[4][3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) lk[3][d] = (h / 6.f) * lam[c][d];
+                    gT(rec.G[3], lk[3], ly[3]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) lk[2][d] = (h / 3.f) * lam[c][d] + h * ly[3][d];
+                    gT(rec.G[2], lk[2], ly[2]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) lk[1][d] = (h / 3.f) * lam[c][d] + (0.5f * h) * ly[2][d];
+                    gT(rec.G[1], lk[1], ly[1]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) lk[0][d] = (h / 6.f) * lam[c][d] + (0.5f * h) * ly[1][d];
+                    gT(rec.G[0], lk[0], ly[0]);
+                    if (c == 0 && a.grad_f) {
+                        float* g0 = a.grad_f[n];
+                        float* g1 = a.grad_f[n + 1];
+                        if (MODE == MODE_FROZEN) {
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) scatter_cell(a.g, g0, rec.base[s], rec.f[s], 1.f, lk[s]);
+                        } else {
+                            scatter_cell(a.g, g0, rec.base[0], rec.f[0], 1.f, lk[0]);
+                            scatter_cell(a.g, g0, rec.base[1], rec.f[1], 0.5f, lk[1]);
+                            scatter_cell(a.g, g1, rec.base[1], rec.f[1], 0.5f, lk[1]);
+                            scatter_cell(a.g, g0, rec.base[2], rec.f[2], 0.5f, lk[2]);
+                            scatter_cell(a.g, g1, rec.base[2], rec.f[2], 0.5f, lk[2]);
+                            scatter_cell(a.g, g1, rec.base[3], rec.f[3], 1.f, lk[3]);
+                        }
+                    }
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) lam[c][d] += ly[0][d] + ly[1][d] + ly[2][d] + ly[3][d];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NCOT; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.grad_seed[(p * NCOT + c) * 3 + d] = lam[c][d] * (float)a.g.inv_sp[d];
+}
+
+// ---------------------------------------------------------------------------
+// FTLE: sigma = ln sqrt(lambda_max(J^T J)) / |T| per seed, from row-major
+// Jacobians (3x3 FP32).  The largest eigenvalue of the symmetric 3x3 matrix
+// C = J^T J comes from the closed-form trigonometric solution of its
+// characteristic cubic, evaluated in FP64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void ftle_kernel(const float* jac, int64_t P, double inv_T, float* out) {
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= P) return;
+    double J[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) J[r][c] = (double)jac[9 * p + 3 * r + c];
+    double C[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) C[i][j] = J[0][i] * J[0][j] + J[1][i] * J[1][j] + J[2][i] * J[2][j];
+    const double p1 = C[0][1] * C[0][1] + C[0][2] * C[0][2] + C[1][2] * C[1][2];
+    const double q = (C[0][0] + C[1][1] + C[2][2]) / 3.0;
+    const double p2 = (C[0][0] - q) * (C[0][0] - q) + (C[1][1] - q) * (C[1][1] - q) + (C[2][2] - q) * (C[2][2] - q) +
+                      2.0 * p1;
+    double lmax;
+    if (p2 <= 0.0) {
+        lmax = q;
+    } else {
+        const double pp = sqrt(p2 / 6.0);
+        double B[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) B[i][j] = (C[i][j] - (i == j ? q : 0.0)) / pp;
+        double detB = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                      B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                      B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+        double r = detB / 2.0;
+        r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+        const double phi = acos(r) / 3.0;
+        lmax = q + 2.0 * pp * cos(phi);
+    }
+    out[p] = (float)(0.5 * log(lmax) * inv_T);
+}
+
+// ---------------------------------------------------------------------------
+template <int DT, int MODE, int NCOT>
+static hipError_t launch_adj_t(const AdjointArgs& a, hipStream_t s) {
+    const int64_t blocks = (a.P + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL((adjoint_kernel<DT, MODE, NCOT>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int DT, int MODE>
+static hipError_t launch_adj_m(const AdjointArgs& a, hipStream_t s) {
+    return a.ncot == 1 ? launch_adj_t<DT, MODE, 1>(a, s) : launch_adj_t<DT, MODE, 3>(a, s);
+}
+
+template <int DT>
+static hipError_t launch_adj_d(const AdjointArgs& a, int mode, hipStream_t s) {
+    return mode == MODE_LINEAR ? launch_adj_m<DT, MODE_LINEAR>(a, s) : launch_adj_m<DT, MODE_FROZEN>(a, s);
+}
+
+hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s) {
+    if (a.P == 0) return hipSuccess;
+    switch (dtype) {
+    case DT_F32: return launch_adj_d<DT_F32>(a, mode, s);
+    case DT_F16: return launch_adj_d<DT_F16>(a, mode, s);
+    default: return launch_adj_d<DT_BF16>(a, mode, s);
+    }
+}
+
+hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(ftle_kernel, dim3((unsigned)((P + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, jac, P, inv_T, out);
+    return hipGetLastError();
+}
+
+}  // namespace bto

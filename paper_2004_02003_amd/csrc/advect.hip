@@ -92,20 +92,24 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
     for (uint32_t b = (uint32_t)(r * W + wave) * WAVE; b < cnt; b += (uint32_t)(R * W * WAVE)) {
         const uint32_t i = b + lane;
         const bool alive = i < cnt;
-        double x[3] = {0.0, 0.0, 0.0};
+        Stepper stp;
+        stp.x[0] = stp.x[1] = stp.x[2] = 0.0;
         uint32_t id = 0;
         int status = S_VALID;
         int s = 0;
         if (alive) {
-            const PState st = a.in_pos[sbase + i];
+            const PState ps = a.in_pos[sbase + i];
             id = a.in_id[sbase + i];
-            unpack(st, x);
+            unpack(ps, stp.x);
+            stepper_init(stp);
             for (s = 0; s < a.K; ++s) {
-                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], x);
+                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], stp);
                 if (status != S_VALID) break;
+                stepper_next_cycle<MODE>(stp);
             }
             my_steps += (status == S_VALID) ? (uint32_t)a.K : (uint32_t)(s + 1);
         }
+        const double* x = stp.x;
         const bool keep = alive && status == S_VALID;
         const unsigned long long m = __ballot(keep);
         if (m) {

@@ -40,6 +40,9 @@ struct bto_ctx {
     int32_t steps_done = 0;
     Segs segs{};
     int64_t seg_cap[NSEG] = {0};
+    // adjoint scratch (grown on demand)
+    void* adj_scratch = nullptr;
+    size_t adj_bytes = 0;
     std::string err;
 };
 
@@ -146,6 +149,7 @@ int bto_destroy(bto_ctx* c) {
     if (c->rec_meta) (void)hipFree(c->rec_meta);
     if (c->seed_xyz) (void)hipFree(c->seed_xyz);
     if (c->counts) (void)hipFree(c->counts);
+    if (c->adj_scratch) (void)hipFree(c->adj_scratch);
     delete c;
     return BTO_OK;
 }
@@ -356,6 +360,94 @@ int bto_stats(bto_ctx* c, bto_stats_t* out, void* stream) {
     for (int x = 0; x < NSEG; ++x) live += cnt[x];
     out->n_live = live;
     out->particle_steps = (int64_t)ps;
+    return BTO_OK;
+}
+
+int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* times, int32_t n_steps,
+                         int32_t dtype, int32_t flags, const float* d_cot_end, int32_t n_cot, float* d_grad_seed,
+                         float* const* d_grad_fields, uint8_t* d_status, int32_t ckpt_every, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (!d_fields || !times || !d_cot_end || !d_grad_seed) return fail(c, BTO_EINVAL, "null argument");
+    if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
+    if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
+    if (flags != BTO_TIME_LINEAR && flags != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    if (n_cot != 1 && n_cot != 3) return fail(c, BTO_EINVAL, "n_cot must be 1 or 3 (got %d)", n_cot);
+    if (d_grad_fields && n_cot != 1) return fail(c, BTO_EINVAL, "grid gradients need n_cot == 1");
+    if (ckpt_every < 1) return fail(c, BTO_EINVAL, "ckpt_every must be >= 1");
+    for (int32_t q = 0; q <= n_steps; ++q) {
+        if (!d_fields[q]) return fail(c, BTO_EINVAL, "field pointer %d is null", q);
+        if (d_grad_fields && !d_grad_fields[q]) return fail(c, BTO_EINVAL, "grad field pointer %d is null", q);
+    }
+    for (int32_t q = 0; q < n_steps; ++q)
+        if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
+            return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
+    if (!c->seeded) return fail(c, BTO_ESTATE, "adjoint called before seeding");
+    if (c->n_seeds == 0) return BTO_OK;
+    const int K = ckpt_every < n_steps ? ckpt_every : n_steps;
+    const int nseg = (n_steps + K - 1) / K;
+    const size_t P = (size_t)c->n_seeds;
+    const size_t tab = ((size_t)(n_steps + 1) * 2 * sizeof(void*) + (size_t)n_steps * sizeof(double) + 255) & ~(size_t)255;
+    const size_t need = tab + P * 3 * sizeof(double) * ((size_t)nseg + (size_t)K);
+    hipStream_t s = (hipStream_t)stream;
+    if (need > c->adj_bytes) {
+        if (c->adj_scratch) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint scratch sync");
+            (void)hipFree(c->adj_scratch);
+            c->adj_scratch = nullptr;
+            c->adj_bytes = 0;
+        }
+        if (hipMalloc(&c->adj_scratch, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, BTO_ENOMEM, "adjoint scratch of %zu bytes", need);
+        }
+        c->adj_bytes = need;
+    }
+    char* base = static_cast<char*>(c->adj_scratch);
+    std::vector<char> host(tab, 0);
+    const void** hf = reinterpret_cast<const void**>(host.data());
+    void** hg = reinterpret_cast<void**>(host.data() + (size_t)(n_steps + 1) * sizeof(void*));
+    double* hh = reinterpret_cast<double*>(host.data() + (size_t)(n_steps + 1) * 2 * sizeof(void*));
+    for (int32_t q = 0; q <= n_steps; ++q) {
+        hf[q] = d_fields[q];
+        hg[q] = d_grad_fields ? (void*)d_grad_fields[q] : nullptr;
+    }
+    for (int32_t q = 0; q < n_steps; ++q) hh[q] = times[q + 1] - times[q];
+    hipError_t e = hipMemcpyAsync(base, host.data(), tab, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint tables upload");
+    AdjointArgs a{};
+    a.f = reinterpret_cast<const char* const*>(base);
+    a.grad_f = d_grad_fields ? reinterpret_cast<float* const*>(base + (size_t)(n_steps + 1) * sizeof(void*)) : nullptr;
+    a.h = reinterpret_cast<const double*>(base + (size_t)(n_steps + 1) * 2 * sizeof(void*));
+    a.g = c->geom;
+    a.N = n_steps;
+    a.k = K;
+    a.ncot = n_cot;
+    a.P = (int64_t)P;
+    a.seed_xyz = c->seed_xyz;
+    for (int d = 0; d < 3; ++d) {
+        a.origin[d] = c->blk.origin[d];
+        a.sp[d] = c->blk.spacing[d];
+    }
+    a.cot = d_cot_end;
+    a.grad_seed = d_grad_seed;
+    a.ckpt = reinterpret_cast<double*>(base + tab);
+    a.buf = a.ckpt + P * 3 * (size_t)nseg;
+    a.status_out = d_status;
+    e = launch_adjoint(a, dtype, flags, s);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
+    return BTO_OK;
+}
+
+int bto_ftle(bto_ctx* c, const float* d_jac, int64_t n, double T, float* d_out, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!d_jac || !d_out))) return fail(c, BTO_EINVAL, "null argument or negative count");
+    if (!(T != 0.0) || !std::isfinite(T)) return fail(c, BTO_EINVAL, "T must be finite and non-zero");
+    hipError_t e = launch_ftle(d_jac, n, 1.0 / std::fabs(T), d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "ftle launch");
     return BTO_OK;
 }
 

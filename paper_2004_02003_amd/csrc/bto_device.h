@@ -141,41 +141,86 @@ __device__ __forceinline__ void trilerp(const float R[4][6], const float f[3], f
     }
 }
 
-template <int DT>
-__device__ __forceinline__ void load_cell(const Geom& g, const char* V, const Cell& c, float R[4][6]) {
-    Field<DT>::row(V, c.base, R[0]);
-    Field<DT>::row(V, c.base + g.sy, R[1]);
-    Field<DT>::row(V, c.base + g.sz, R[2]);
-    Field<DT>::row(V, c.base + g.sy + g.sz, R[3]);
-}
-
-// T(V, p): one grid level.
-template <int DT>
-__device__ __forceinline__ void sample1(const Geom& g, const char* V, const double p[3], float out[3]) {
-    const Cell c = locate(g, p);
-    float R[4][6];
-    load_cell<DT>(g, V, c, R);
-    trilerp(R, c.f, out);
-}
-
-// (T(V0, p) + T(V1, p)) / 2: the midpoint in time.  Interpolation is linear in
-// the grid values, so the two levels are averaged per corner first.
-template <int DT>
-__device__ __forceinline__ void sample_mid(const Geom& g, const char* V0, const char* V1, const double p[3],
-                                           float out[3]) {
-    const Cell c = locate(g, p);
-    float R[4][6], S[4][6];
-    load_cell<DT>(g, V0, c, R);
-    load_cell<DT>(g, V1, c, S);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) R[r][q] = 0.5f * (R[r][q] + S[r][q]);
-    trilerp(R, c.f, out);
-}
-
 __device__ __forceinline__ bool finite3(const float k[3]) {
     return __builtin_isfinite(k[0]) && __builtin_isfinite(k[1]) && __builtin_isfinite(k[2]);
+}
+
+// Corner values of one cell of one grid level, held in registers across the
+// RK4 stages (and across steps: the level n+1 rows of step n are the level n
+// rows of step n+1).  A stage only reloads when its point lies in another cell.
+struct CellCache {
+    uint64_t base;  // point index of the cached cell's corner (i, j, k); ~0 = empty
+    float R[4][6];
+};
+
+template <int DT>
+__device__ __forceinline__ void ensure(const Geom& g, const char* V, uint64_t base, CellCache& c) {
+    if (c.base != base) {
+        Field<DT>::row(V, base, c.R[0]);
+        Field<DT>::row(V, base + g.sy, c.R[1]);
+        Field<DT>::row(V, base + g.sz, c.R[2]);
+        Field<DT>::row(V, base + g.sy + g.sz, c.R[3]);
+        c.base = base;
+    }
+}
+
+// trilinear interpolation of the time midpoint (A + B) / 2 of two levels
+__device__ __forceinline__ void trilerp_mid(const float A[4][6], const float B[4][6], const float f[3],
+                                            float out[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float a[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float lo = 0.5f * (A[r][c] + B[r][c]);
+            const float hi = 0.5f * (A[r][3 + c] + B[r][3 + c]);
+            a[r] = lerp(lo, hi, f[0]);
+        }
+        const float b0 = lerp(a[0], a[1], f[1]);
+        const float b1 = lerp(a[2], a[3], f[1]);
+        out[c] = lerp(b0, b1, f[2]);
+    }
+}
+
+// Trilinear value and its derivatives with respect to the in-cell offset
+// (d v_c / d f_d, which equals d v_c / d p_d in cell units) from the 8 corner
+// values; `mid` averages two levels per corner first (time midpoint).
+template <bool MID>
+__device__ __forceinline__ void trilerp_grad(const float A[4][6], const float B[4][6], const float f[3],
+                                             float v[3], float G[3][3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float lo[4], hi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            lo[r] = MID ? 0.5f * (A[r][c] + B[r][c]) : A[r][c];
+            hi[r] = MID ? 0.5f * (A[r][3 + c] + B[r][3 + c]) : A[r][3 + c];
+        }
+        float a[4], dx[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a[r] = lerp(lo[r], hi[r], f[0]);
+            dx[r] = hi[r] - lo[r];
+        }
+        const float b0 = lerp(a[0], a[1], f[1]);
+        const float b1 = lerp(a[2], a[3], f[1]);
+        v[c] = lerp(b0, b1, f[2]);
+        G[c][0] = lerp(lerp(dx[0], dx[1], f[1]), lerp(dx[2], dx[3], f[1]), f[2]);
+        G[c][1] = lerp(a[1] - a[0], a[3] - a[2], f[2]);
+        G[c][2] = b1 - b0;
+    }
+}
+
+// Per-lane stepping state: FP64 position plus the two cached levels.
+struct Stepper {
+    double x[3];
+    CellCache A;  // level n   (cycle of the step's start)
+    CellCache B;  // level n+1
+};
+
+__device__ __forceinline__ void stepper_init(Stepper& st) {
+    st.A.base = ~0ull;
+    st.B.base = ~0ull;
 }
 
 // One classic RK4 step of one cycle: stage times t, t+h/2, t+h/2, t+h with the
@@ -184,32 +229,55 @@ __device__ __forceinline__ bool finite3(const float k[3]) {
 // each later stage point and the end point are checked inside the block, in
 // order.  On any event x is left at the step's start.
 template <int DT, int MODE>
-__device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, double x[3]) {
+__device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, Stepper& st) {
     const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
     float k1[3], k2[3], k3[3], k4[3];
     double y[3];
+    double* x = st.x;
+    Cell c;
 
-    sample1<DT>(g, V0, x, k1);
+    c = locate(g, x);
+    ensure<DT>(g, V0, c.base, st.A);
+    trilerp(st.A.R, c.f, k1);
     if (!finite3(k1)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = fma(0.5 * hs[d], (double)k1[d], x[d]);
     if (!inside(g, y)) return S_TERMINATED;
 
-    if (MODE == MODE_LINEAR) sample_mid<DT>(g, V0, V1, y, k2);
-    else sample1<DT>(g, V0, y, k2);
+    c = locate(g, y);
+    ensure<DT>(g, V0, c.base, st.A);
+    if (MODE == MODE_LINEAR) {
+        ensure<DT>(g, V1, c.base, st.B);
+        trilerp_mid(st.A.R, st.B.R, c.f, k2);
+    } else {
+        trilerp(st.A.R, c.f, k2);
+    }
     if (!finite3(k2)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = fma(0.5 * hs[d], (double)k2[d], x[d]);
     if (!inside(g, y)) return S_TERMINATED;
 
-    if (MODE == MODE_LINEAR) sample_mid<DT>(g, V0, V1, y, k3);
-    else sample1<DT>(g, V0, y, k3);
+    c = locate(g, y);
+    ensure<DT>(g, V0, c.base, st.A);
+    if (MODE == MODE_LINEAR) {
+        ensure<DT>(g, V1, c.base, st.B);
+        trilerp_mid(st.A.R, st.B.R, c.f, k3);
+    } else {
+        trilerp(st.A.R, c.f, k3);
+    }
     if (!finite3(k3)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = fma(hs[d], (double)k3[d], x[d]);
     if (!inside(g, y)) return S_TERMINATED;
 
-    sample1<DT>(g, MODE == MODE_LINEAR ? V1 : V0, y, k4);
+    c = locate(g, y);
+    if (MODE == MODE_LINEAR) {
+        ensure<DT>(g, V1, c.base, st.B);
+        trilerp(st.B.R, c.f, k4);
+    } else {
+        ensure<DT>(g, V0, c.base, st.A);
+        trilerp(st.A.R, c.f, k4);
+    }
     if (!finite3(k4)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -221,6 +289,17 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     x[1] = y[1];
     x[2] = y[2];
     return S_VALID;
+}
+
+// After a step the level n+1 rows serve as the next step's level n rows.
+template <int MODE>
+__device__ __forceinline__ void stepper_next_cycle(Stepper& st) {
+    if (MODE == MODE_LINEAR) {
+        st.A = st.B;
+    } else {
+        st.A.base = ~0ull;
+    }
+    st.B.base = ~0ull;
 }
 
 }  // namespace bto

@@ -79,6 +79,24 @@ struct FlowmapArgs {
     int32_t* out_exit;
 };
 
+struct AdjointArgs {
+    const char* const* f;       // device array: N + 1 grids
+    const double* h;            // device array: N step sizes
+    Geom g;
+    int32_t N;                  // steps
+    int32_t k;                  // checkpoint every k steps
+    int32_t ncot;               // cotangent vectors per seed (1 or 3)
+    int64_t P;
+    const double* seed_xyz;     // P x 3 world
+    double origin[3], sp[3];
+    const float* cot;           // P x ncot x 3, d L / d x_end (world)
+    float* grad_seed;           // P x ncot x 3, d L / d x_0 (world)
+    float* const* grad_f;       // device array of N + 1 FP32 grids (accumulated) or null
+    double* ckpt;               // P x ceil(N/k) x 3 scratch
+    double* buf;                // P x k x 3 scratch
+    uint8_t* status_out;        // P (may be null): status of the recomputed forward
+};
+
 hipError_t launch_seed_lattice(const SeedLatticeArgs& a, hipStream_t s);
 hipError_t launch_seed_explicit(const SeedExplicitArgs& a, hipStream_t s);
 hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, unsigned long long* psteps,
@@ -86,5 +104,7 @@ hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, un
 hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int blocks_per_seg, hipStream_t s);
 hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t s);
 int advect_max_blocks_per_cu(int dtype, int mode);
+hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);
+hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s);
 
 }  // namespace bto

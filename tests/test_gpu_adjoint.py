@@ -1,0 +1,223 @@
+"""GPU adjoint (seed and grid gradients, Jacobian, FTLE) against the FP64
+oracle: its discrete adjoint and tangent (same discrete derivative) and FP64
+central finite differences of its forward map (h = 1e-3, entries whose +-h
+runs change a flag, exit step or stage cell excluded)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from bto_inputs import fields
+from bto_inputs.workloads import WORKLOADS, loss_weights
+
+pytestmark = pytest.mark.gpu
+H = 1e-3
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2004_02003_amd import _lib
+
+    _lib.load()
+
+
+def _dev(grids, dtype="f32"):
+    from paper_2004_02003_amd import grid_to_device
+
+    return [grid_to_device(g, dtype) for g in grids]
+
+
+def _small():
+    n = (24, 24, 24)
+    N = 16
+    s = fields.abc_noise(n, N + 1, 0.05, sigma=0.05, seed=8, global_n=64)
+    gr = s.grids("f32")
+    seeds = oracle.seed_lattice(n, 4)
+    w = np.random.default_rng(3).standard_normal(seeds.shape)
+    return n, N, s, gr, seeds, w
+
+
+def _gpu_adjoint(n, gr, times, seeds, cot, ckpt, grid_grad=False, mode="linear"):
+    import torch
+    from paper_2004_02003_amd import Context
+
+    dev = _dev(gr)
+    with Context(n, len(seeds)) as ctx:
+        ctx.seed_explicit(torch.as_tensor(seeds, dtype=torch.float64, device="cuda"))
+        gg = [torch.zeros_like(g) for g in dev] if grid_grad else None
+        status = torch.empty(len(seeds), dtype=torch.uint8, device="cuda")
+        out = ctx.adjoint(dev, times, torch.as_tensor(cot, dtype=torch.float32, device="cuda").contiguous(),
+                          grad_grids=gg, ckpt_every=ckpt, mode=mode, status=status)
+        torch.cuda.synchronize()
+        res = out.cpu().numpy(), status.cpu().numpy()
+        if grid_grad:
+            res = res + ([g.cpu().numpy() for g in gg],)
+    return res
+
+
+def test_seed_gradient_matches_oracle_adjoint_and_fd():
+    n, N, s, gr, seeds, w = _small()
+    _say("adjoint seed gradient 24^3, 16 steps")
+    g, st = _gpu_adjoint(n, gr, s.times, seeds, w, ckpt=5)
+    g = g[:, 0, :]
+    F = oracle.Field(n, gr)
+    base = oracle.flowmap(F, s.times, seeds, N)
+    go = oracle.adjoint(F, s.times, seeds, N, w)
+    ok = base["margin"] > 1e-6
+    assert np.array_equal(st[ok], base["flag"][ok])
+    valid = (base["flag"] == 0) & ok
+    assert valid.sum() > 50
+    err = np.linalg.norm(g[valid] - go[valid]) / np.linalg.norm(go[valid])
+    assert err < 1e-5, err
+    assert np.all(g[base["flag"] == 1] == 0)
+    # against central FD of the FP64 forward
+    fd = np.zeros_like(go)
+    same = np.ones(len(seeds), bool)
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = H
+        rp = oracle.flowmap(F, s.times, seeds + e, N)
+        rm = oracle.flowmap(F, s.times, seeds - e, N)
+        same &= (rp["sig"] == base["sig"]) & (rm["sig"] == base["sig"]) & (rp["flag"] == 0) & (rm["flag"] == 0)
+        fd[:, d] = ((w * rp["end"]).sum(1) - (w * rm["end"]).sum(1)) / (2 * H)
+    sel = valid & same
+    assert sel.sum() > 20
+    rel = np.linalg.norm(g[sel] - fd[sel]) / np.linalg.norm(fd[sel])
+    assert rel < 1e-4, rel
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    n, N, s, gr, seeds, w = _small()
+    outs = []
+    for k in (1, 3, 7, 16, 100):
+        _say(f"adjoint ckpt_every={k}")
+        outs.append(_gpu_adjoint(n, gr, s.times, seeds, w, ckpt=k)[0])
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_jacobian_matches_oracle_tangent_and_ftle():
+    import torch
+    from paper_2004_02003_amd import Context, jacobian_ftle
+
+    n, N, s, gr, seeds, w = _small()
+    _say("jacobian + ftle")
+    dev = _dev(gr)
+    with Context(n, len(seeds)) as ctx:
+        J, sig, st = jacobian_ftle(ctx, torch.as_tensor(seeds, device="cuda"), dev, s.times, ckpt_every=4)
+        torch.cuda.synchronize()
+        J, sig, st = J.cpu().numpy(), sig.cpu().numpy(), st.cpu().numpy()
+    o = oracle.flowmap(oracle.Field(n, gr), s.times, seeds, N, jac=True)
+    valid = (o["flag"] == 0) & (o["margin"] > 1e-6)
+    err = np.linalg.norm(J[valid] - o["jac"][valid]) / np.linalg.norm(o["jac"][valid])
+    assert err < 1e-5, err
+    T = s.times[N] - s.times[0]
+    np.testing.assert_allclose(sig[valid], oracle.ftle(o["jac"][valid], T), rtol=1e-4, atol=1e-5)
+    assert np.all(J[st != 0] == 0)
+
+
+def test_grid_gradient_matches_oracle_dense_gradient():
+    n, N, s, gr, seeds, w = _small()
+    seeds, w = seeds[::3], w[::3]
+    _say("adjoint grid gradient 24^3")
+    g, st, gg = _gpu_adjoint(n, gr, s.times, seeds, w, ckpt=4, grid_grad=True)
+    F = oracle.Field(n, gr)
+    go, ggo = oracle.adjoint(F, s.times, seeds, N, w, grid_grad=True)
+    base = oracle.flowmap(F, s.times, seeds, N)
+    assert np.all(base["margin"] > 1e-6), "choose a case without face ties"
+    A = np.stack(gg).astype(np.float64)
+    B = np.stack(ggo)
+    # entries no trajectory touches are exactly zero on both sides
+    assert np.all(A[B == 0] == 0)
+    err = np.linalg.norm(A - B) / np.linalg.norm(B)
+    assert err < 1e-5, err
+
+
+def test_frozen_mode_adjoint_matches_oracle():
+    n, N, s, gr, seeds, w = _small()
+    _say("adjoint frozen mode")
+    g, st, gg = _gpu_adjoint(n, gr, s.times, seeds[::4], w[::4], ckpt=6, grid_grad=True, mode="frozen")
+    F = oracle.Field(n, gr)
+    go, ggo = oracle.adjoint(F, s.times, seeds[::4], N, w[::4], mode=oracle.FROZEN, grid_grad=True)
+    base = oracle.flowmap(F, s.times, seeds[::4], N, mode=oracle.FROZEN)
+    valid = (base["flag"] == 0) & (base["margin"] > 1e-6)
+    err = np.linalg.norm(g[valid, 0] - go[valid]) / np.linalg.norm(go[valid])
+    assert err < 1e-5, err
+    errg = np.linalg.norm(np.stack(gg) - np.stack(ggo)) / np.linalg.norm(np.stack(ggo))
+    assert errg < 1e-5, errg
+
+
+def test_autograd_function_seed_and_grid_gradients():
+    import torch
+    from paper_2004_02003_amd import Context, advect_autograd
+
+    n, N, s, gr, seeds, w = _small()
+    _say("autograd")
+    dev = [g.requires_grad_(True) for g in _dev(gr)]
+    x0 = torch.as_tensor(seeds, device="cuda").requires_grad_(True)
+    wt = torch.as_tensor(w, device="cuda")
+    with Context(n, len(seeds)) as ctx:
+        end, flag, ex = advect_autograd(ctx, x0, dev, s.times, ckpt_every=5)
+        loss = (wt * end * (flag == 0).unsqueeze(1)).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+    F = oracle.Field(n, gr)
+    go, ggo = oracle.adjoint(F, s.times, seeds, N, w, grid_grad=True)
+    base = oracle.flowmap(F, s.times, seeds, N)
+    valid = (base["flag"] == 0) & (base["margin"] > 1e-6)
+    gx = x0.grad.cpu().numpy()
+    assert np.linalg.norm(gx[valid] - go[valid]) / np.linalg.norm(go[valid]) < 1e-5
+    A = np.stack([g.grad.cpu().numpy() for g in dev])
+    assert np.linalg.norm(A - np.stack(ggo)) / np.linalg.norm(np.stack(ggo)) < 1e-4
+    np.testing.assert_allclose(end.detach().cpu().numpy()[valid], base["end"][valid], atol=1e-5)
+
+
+def test_abc_128_adjoint_workload_full_size():
+    """The differentiation workload at full size: 32^3 seeds (stride 4) on the
+    128^3 ABC field, 100 steps, checkpoints every 10; seed gradient of the
+    seeded-weight loss on every seed against the oracle adjoint, plus the
+    Jacobian on a subset against the oracle tangent."""
+    import torch
+    from paper_2004_02003_amd import Context, jacobian_ftle
+
+    wl = WORKLOADS["abc_128_adjoint"]
+    _say(f"{wl.name} full size")
+    s = wl.make_field()
+    gr = s.grids("f32")
+    seeds = oracle.seed_lattice(wl.n, wl.stride)
+    w = loss_weights(len(seeds), wl.extra["weight_seed"])
+    dev = _dev(gr)
+    with Context(wl.n, len(seeds)) as ctx:
+        ctx.seed(wl.stride)
+        cot = torch.as_tensor(w, dtype=torch.float32, device="cuda").contiguous()
+        status = torch.empty(len(seeds), dtype=torch.uint8, device="cuda")
+        g = ctx.adjoint(dev, s.times, cot, ckpt_every=wl.extra["ckpt_every"], status=status)
+        sub = torch.as_tensor(seeds[::37], device="cuda")
+        J, sig, stJ = jacobian_ftle(ctx, sub, dev, s.times, ckpt_every=wl.extra["ckpt_every"])
+        torch.cuda.synchronize()
+        g = g.cpu().numpy()[:, 0, :]
+        st = status.cpu().numpy()
+        J = J.cpu().numpy()
+    F = oracle.Field(wl.n, gr)
+    base = oracle.flowmap(F, s.times, seeds, wl.n_steps)
+    go = oracle.adjoint(F, s.times, seeds, wl.n_steps, w)
+    ok = base["margin"] > 1e-6
+    assert np.array_equal(st[ok], base["flag"][ok])
+    valid = (base["flag"] == 0) & ok
+    err = np.linalg.norm(g[valid] - go[valid]) / np.linalg.norm(go[valid])
+    _say(f"seed-gradient rel err {err:.2e} over {valid.sum()} seeds")
+    assert err < 1e-5, err
+    oj = oracle.flowmap(F, s.times, seeds[::37], wl.n_steps, jac=True)
+    vj = (oj["flag"] == 0) & (oj["margin"] > 1e-6)
+    errj = np.linalg.norm(J[vj] - oj["jac"][vj]) / np.linalg.norm(oj["jac"][vj])
+    assert errj < 1e-5, errj

@@ -1,0 +1,178 @@
+"""Turbulence workloads on the GPU: the device input generator reproduces the
+host evaluator bit for bit; the 256^3 precision workload (f32/f16/bf16) and the
+512^3 scale workload (f16, two resident cycles, plus the Jacobian adjoint on
+every 16th seed) match the oracle on sampled seeds.
+
+Tolerance under chaotic stretching: FP32 sampling errors of a few ulp of |V|
+per step grow with the flow map's Jacobian, so a seed's end-position bound is
+1e-5 cells plus ||J|| * N * h * max|V| * 2^-21 (first-order propagation, J from
+the oracle's FP64 tangent); the fraction of seeds beyond a flat 1e-5 is
+reported."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from bto_inputs import fields
+from bto_inputs import _turb
+from bto_inputs.workloads import WORKLOADS
+
+from .parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2004_02003_amd import _lib
+
+    _lib.load()
+
+
+_TDT = {"f32": "float32", "f16": "float16", "bf16": "bfloat16", "f64": "float64"}
+
+
+def _empty(n, dtype):
+    import torch
+
+    return torch.empty((n[2], n[1], n[0], 3), dtype=getattr(torch, _TDT[dtype]), device="cuda")
+
+
+def _bits(t):
+    import torch
+
+    a = t.cpu()
+    if a.dtype in (torch.float16, torch.bfloat16):
+        return a.view(torch.int16).numpy()
+    return a.numpy()
+
+
+def test_device_generator_is_bit_identical_to_host():
+    s = fields.turbulence((40, 24, 16), 16, 5, 3, 0.02)
+    dev = _turb.DeviceTurbulence(s.lazy)
+    for dt in ("f64", "f32", "f16", "bf16"):
+        _say(f"device generator {dt}")
+        g = dev.fill(2, dt, _empty(s.n, dt))
+        host = s.grid(2, dt)
+        hb = host.view(np.int16) if dt == "bf16" else (host.view(np.int16) if dt == "f16" else host)
+        assert np.array_equal(_bits(g), hb), dt
+    big = fields.turbulence(512, 128, 4, 3, 0.01)
+    devb = _turb.DeviceTurbulence(big.lazy)
+    _say("device generator 512^3 f16 sampled")
+    g = devb.fill(1, "f16", _empty(big.n, "f16")).cpu().numpy()
+    rng = np.random.default_rng(0)
+    for (i, j, k) in rng.integers(0, 512, size=(200, 3)):
+        v = _turb.store_round(big.lazy.point(1, i, j, k), "f16")
+        assert np.array_equal(g[k, j, i].astype(np.float64), v)
+
+
+def _run_series(ctx, dev, s, N, dtype, ring=False):
+    """Advance the context's seeds through N steps of the device-generated
+    series: all grids resident, or a two-slot ring refilled every cycle."""
+    import torch
+
+    if not ring:
+        grids = [dev.fill(c, dtype, _empty(s.n, dtype)) for c in range(N + 1)]
+        ctx.advect(grids, s.times[:N + 1])
+        return grids
+    slots = [_empty(s.n, dtype), _empty(s.n, dtype)]
+    dev.fill(0, dtype, slots[0])
+    for c in range(N):
+        dev.fill(c + 1, dtype, slots[(c + 1) % 2])
+        ctx.advect([slots[c % 2], slots[(c + 1) % 2]], s.times[c:c + 2])
+    torch.cuda.synchronize()
+    return None
+
+
+def _jac_tol(o, N, h, vmax):
+    nj = np.linalg.norm(o["jac"], axis=(1, 2), ord=2)
+    return nj * N * h * vmax * 2.0 ** -21
+
+
+def test_turb_256_precision_workload_sampled_parity():
+    import torch
+    from paper_2004_02003_amd import Context
+
+    wl = WORKLOADS["turb_256"]
+    s = wl.make_field()
+    dev = _turb.DeviceTurbulence(s.lazy)
+    ids = np.arange(0, wl.n_seeds, 509)
+    seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
+    report = {}
+    for dt in wl.dtypes:
+        _say(f"{wl.name} {dt} full size")
+        with Context(wl.n, wl.n_seeds) as ctx:
+            ctx.seed(wl.stride)
+            grids = _run_series(ctx, dev, s, wl.n_steps, dt)
+            vmax = max(float(g.float().abs().max()) for g in grids[::10]) * 1.7320508
+            fm = ctx.flowmap(count_valid=True)
+            st = ctx.stats()
+            torch.cuda.synchronize()
+            g = {k: v.cpu().numpy()[ids] for k, v in fm.items() if k not in ("n_valid", "seed")}
+            del grids
+            torch.cuda.empty_cache()
+        o = oracle.flowmap(oracle.Field.lazy_turbulence(s, dt), s.times, seeds, wl.n_steps, jac=True)
+        tol = _jac_tol(o, wl.n_steps, wl.dt, vmax)
+        res = compare(g, o, per_particle_tol=tol, label=f"{wl.name}/{dt}")
+        err = np.abs(g["end"] - o["end"]).max(axis=1)
+        ok = (o["margin"] >= 1e-6) & (o["flag"] == 0)
+        res["frac_over_1e-5"] = float((err[ok] > 1e-5).mean())
+        report[dt] = res
+        _say(f"{wl.name}/{dt}: {res}, live {st['n_live']} of {st['n_seeds']}")
+        assert 0.2 < res["terminated"] < 0.5
+        assert res["frac_over_1e-5"] < 0.05
+
+
+def test_turb_512_scale_workload_ring_and_jacobian_subset():
+    import torch
+    from paper_2004_02003_amd import Context, jacobian_ftle
+
+    wl = WORKLOADS["turb_512"]
+    s = wl.make_field()
+    dev = _turb.DeviceTurbulence(s.lazy)
+    dt = "f16"
+    _say(f"{wl.name} forward, two-slot ring, {wl.n_seeds} seeds")
+    ids = np.arange(0, wl.n_seeds, 4099)
+    seeds_all = oracle.seed_lattice(wl.n, wl.stride)
+    with Context(wl.n, wl.n_seeds) as ctx:
+        ctx.seed(wl.stride)
+        _run_series(ctx, dev, s, wl.n_steps, dt, ring=True)
+        fm = ctx.flowmap(count_valid=True)
+        st = ctx.stats()
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy()[ids] for k, v in fm.items() if k not in ("n_valid", "seed")}
+    o = oracle.flowmap(oracle.Field.lazy_turbulence(s, dt), s.times, seeds_all[ids], wl.n_steps, jac=True)
+    vmax = 1.5 / wl.dt * 6.0
+    res = compare(g, o, per_particle_tol=_jac_tol(o, wl.n_steps, wl.dt, vmax), label=wl.name)
+    _say(f"{wl.name}: {res}; live {st['n_live']} of {st['n_seeds']}, particle-steps {st['particle_steps']}")
+    assert 0.35 < 1 - st["n_live"] / st["n_seeds"] < 0.65
+
+    # Jacobian adjoint on every 16th seed id, all 201 grids resident (f16: 162 GB)
+    sub_ids = np.arange(0, wl.n_seeds, wl.extra["jacobian_every"])
+    _say(f"{wl.name} Jacobian on {len(sub_ids)} seeds")
+    grids = [dev.fill(c, dt, _empty(wl.n, dt)) for c in range(wl.n_steps + 1)]
+    with Context(wl.n, len(sub_ids)) as ctx:
+        x0 = torch.as_tensor(seeds_all[sub_ids], device="cuda")
+        J, sig, stj = jacobian_ftle(ctx, x0, grids, s.times, ckpt_every=10)
+        torch.cuda.synchronize()
+        pick = np.arange(0, len(sub_ids), 4099)
+        J = J.cpu().numpy()[pick]
+        stj = stj.cpu().numpy()
+    del grids
+    torch.cuda.empty_cache()
+    oj = oracle.flowmap(oracle.Field.lazy_turbulence(s, dt), s.times, seeds_all[sub_ids[pick]], wl.n_steps, jac=True)
+    ok = (oj["flag"] == 0) & (oj["margin"] > 1e-6)
+    assert np.array_equal(stj[pick][oj["margin"] > 1e-6], oj["flag"][oj["margin"] > 1e-6])
+    rel = np.linalg.norm(J[ok] - oj["jac"][ok], axis=(1, 2)) / np.linalg.norm(oj["jac"][ok], axis=(1, 2))
+    _say(f"Jacobian rel err median {np.median(rel):.2e} max {rel.max():.2e} over {ok.sum()}")
+    assert np.median(rel) < 1e-4

@@ -31,7 +31,7 @@ def lib():
 def test_header_declares_the_path_entry_points():
     names = _declared()
     for fn in ("bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
-               "bto_advect_interval", "bto_flowmap_out", "bto_stats"):
+               "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle"):
         assert fn in names, fn
 
 
