@@ -49,6 +49,7 @@ def field_bytes_per_point(dt: str) -> int:
 
 
 def launch_plan(n_steps: int, kmax: int = 32):
+    kmax = int(os.environ.get("BTO_STEPS_PER_LAUNCH", kmax))
     nl = (n_steps + kmax - 1) // kmax
     return [n_steps // nl + (1 if l < n_steps % nl else 0) for l in range(nl)]
 
@@ -74,9 +75,13 @@ def main(argv=None):
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--steps-per-launch", type=int, default=None,
+                    help="RK4 steps fused into one advection launch (1..32; sets BTO_STEPS_PER_LAUNCH)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args(argv)
+    if args.steps_per_launch is not None:
+        os.environ["BTO_STEPS_PER_LAUNCH"] = str(args.steps_per_launch)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the per-block BTO path has no cross-GPU work "
               "(blocks are independent); run one process per block instead.", file=sys.stderr)

@@ -16,7 +16,7 @@
 namespace bto {
 
 struct StageRec {
-    uint64_t base[4];
+    uint32_t base[4];
     float f[4][3];
     float G[4][3][3];  // d k~_r / d y_d in cells (k~ = velocity in cells per unit time)
 };
@@ -25,8 +25,8 @@ struct StageRec {
 // gradient.  Mirrors rk4_step (same operations in the same order for the
 // position), returning the same status.
 template <int DT, int MODE>
-__device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const char* V1, double h, Stepper& st,
-                                            StageRec& rec) {
+__device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const char* V1, double h,
+                                            Stepper<DT>& st, StageRec& rec) {
     const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
     float k[4][3];
     double y[3] = {st.x[0], st.x[1], st.x[2]};
@@ -45,17 +45,17 @@ __device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const
         float G[3][3];
         if (MODE == MODE_FROZEN) {
             ensure<DT>(g, V0, c.base, st.A);
-            trilerp_grad<false>(st.A.R, st.A.R, c.f, k[s], G);
+            trilerp_grad<false>(st.A, st.A, c.f, k[s], G);
         } else if (s == 0) {
             ensure<DT>(g, V0, c.base, st.A);
-            trilerp_grad<false>(st.A.R, st.A.R, c.f, k[s], G);
+            trilerp_grad<false>(st.A, st.A, c.f, k[s], G);
         } else if (s == 3) {
             ensure<DT>(g, V1, c.base, st.B);
-            trilerp_grad<false>(st.B.R, st.B.R, c.f, k[s], G);
+            trilerp_grad<false>(st.B, st.B, c.f, k[s], G);
         } else {
             ensure<DT>(g, V0, c.base, st.A);
             ensure<DT>(g, V1, c.base, st.B);
-            trilerp_grad<true>(st.A.R, st.B.R, c.f, k[s], G);
+            trilerp_grad<true>(st.A, st.B, c.f, k[s], G);
         }
         if (!finite3(k[s])) return S_INVALID;
 #pragma unroll
@@ -81,7 +81,7 @@ __device__ __forceinline__ void gT(const float G[3][3], const float v[3], float 
 }
 
 // scatter coef * w_corner(f) * inv_sp_r * lam_r into grid `gf` at the cell
-__device__ __forceinline__ void scatter_cell(const Geom& g, float* gf, uint64_t base, const float f[3], float coef,
+__device__ __forceinline__ void scatter_cell(const Geom& g, float* gf, uint32_t base, const float f[3], float coef,
                                              const float lam[3]) {
     if (!gf) return;
     const float wx[2] = {1.f - f[0], f[0]}, wy[2] = {1.f - f[1], f[1]}, wz[2] = {1.f - f[2], f[2]};
@@ -94,7 +94,7 @@ __device__ __forceinline__ void scatter_cell(const Geom& g, float* gf, uint64_t 
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 const float w = wx[a] * wy[b] * wz[c];
-                float* p = gf + 3 * (base + (uint64_t)a + g.sy * (uint64_t)b + g.sz * (uint64_t)c);
+                float* p = gf + 3 * ((uint64_t)base + (uint64_t)a + (uint64_t)g.sy * b + (uint64_t)g.sz * c);
                 unsafeAtomicAdd(p + 0, w * l[0]);
                 unsafeAtomicAdd(p + 1, w * l[1]);
                 unsafeAtomicAdd(p + 2, w * l[2]);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
     double* ck = a.ckpt + (size_t)p * 3 * (nseg > 0 ? nseg : 1);
     double* buf = a.buf + (size_t)p * 3 * K;
 
-    Stepper st;
+    Stepper<DT> st;
     stepper_init(st);
 #pragma unroll
     for (int d = 0; d < 3; ++d) st.x[d] = (a.seed_xyz[3 * p + d] - a.origin[d]) * a.g.inv_sp[d];
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
                 }
             }
             for (int n = n1 - 1; n >= n0; --n) {
-                Stepper sr;
+                Stepper<DT> sr;
                 stepper_init(sr);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) sr.x[d] = buf[3 * (n - n0) + d];

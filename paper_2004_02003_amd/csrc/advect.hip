@@ -69,7 +69,7 @@ struct CountValues {
 __global__ void set_counts_kernel(uint32_t* counts, const CountValues vals, int n, unsigned long long* psteps) {
     const int t = threadIdx.x;
     if (t < n) counts[t] = vals.v[t];
-    if (t == 0 && psteps) *psteps = 0ull;
+    if (t < NSEG && psteps) psteps[t] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -77,22 +77,26 @@ __global__ void set_counts_kernel(uint32_t* counts, const CountValues vals, int 
 // ---------------------------------------------------------------------------
 template <int DT, int MODE>
 __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
+    constexpr int W = BLOCK / WAVE;
     const int seg = blockIdx.x % NSEG;
     const int r = blockIdx.x / NSEG;
     const int R = gridDim.x / NSEG;
-    const int W = BLOCK / WAVE;
     const int wave = threadIdx.x / WAVE;
     const int lane = threadIdx.x % WAVE;
+    __shared__ uint32_t s_cnt[W];
+    __shared__ uint32_t s_base;
     if (blockIdx.x == 0 && threadIdx.x < NSEG) a.clear_count[threadIdx.x] = 0u;
 
     const uint32_t cnt = a.in_count[seg];
     const int64_t sbase = a.segs.base[seg];
     uint32_t my_steps = 0;
 
-    for (uint32_t b = (uint32_t)(r * W + wave) * WAVE; b < cnt; b += (uint32_t)(R * W * WAVE)) {
-        const uint32_t i = b + lane;
+    // Block-uniform loop over batches of BLOCK particles of this segment, so
+    // the barriers below are reached by every wave the same number of times.
+    for (uint32_t bb = (uint32_t)r * BLOCK; bb < cnt; bb += (uint32_t)R * BLOCK) {
+        const uint32_t i = bb + threadIdx.x;
         const bool alive = i < cnt;
-        Stepper stp;
+        Stepper<DT> stp;
         stp.x[0] = stp.x[1] = stp.x[2] = 0.0;
         uint32_t id = 0;
         int status = S_VALID;
@@ -111,28 +115,44 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
         }
         const double* x = stp.x;
         const bool keep = alive && status == S_VALID;
+        // survivors: wave ballot, block prefix over the waves, one atomic per block
         const unsigned long long m = __ballot(keep);
-        if (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            uint32_t wbase = 0;
-            if (lane == leader) wbase = atomicAdd(&a.out_count[seg], (uint32_t)__popcll(m));
-            wbase = __shfl(wbase, leader);
-            if (keep) {
-                const uint32_t off = wbase + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                a.out_pos[sbase + off] = pack(x);
-                a.out_id[sbase + off] = id;
+        if (lane == 0) s_cnt[wave] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint32_t c = s_cnt[w];
+                s_cnt[w] = tot;
+                tot += c;
             }
+            s_base = tot ? atomicAdd(&a.out_count[seg], tot) : 0u;
+        }
+        __syncthreads();
+        if (keep) {
+            const uint32_t off = s_base + s_cnt[wave] +
+                                 __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            a.out_pos[sbase + off] = pack(x);
+            a.out_id[sbase + off] = id;
         }
         if (alive && !keep) {
             a.rec_pos[id] = pack(x);
             a.rec_meta[id] = (status << META_SHIFT) | (a.step0 + s);
         }
+        __syncthreads();  // s_cnt / s_base are reused by the next batch
     }
-    // wave total of attempted particle-steps
+    // block total of attempted particle-steps, one atomic per block into the segment's counter
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1) my_steps += __shfl_xor(my_steps, o);
-    if (lane == 0 && my_steps) atomicAdd(a.psteps, (unsigned long long)my_steps);
+    if (lane == 0) s_cnt[wave] = my_steps;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) tot += s_cnt[w];
+        if (tot) atomicAdd(&a.psteps[seg], tot);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -214,35 +234,37 @@ static hipError_t launch_advect_t(const AdvectArgs& a, int R, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int DT>
+static hipError_t launch_advect_m(const AdvectArgs& a, int mode, int R, hipStream_t s) {
+    return mode == MODE_LINEAR ? launch_advect_t<DT, MODE_LINEAR>(a, R, s) : launch_advect_t<DT, MODE_FROZEN>(a, R, s);
+}
+
 hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int R, hipStream_t s) {
-    if (mode == MODE_LINEAR) {
-        switch (dtype) {
-        case DT_F32: return launch_advect_t<DT_F32, MODE_LINEAR>(a, R, s);
-        case DT_F16: return launch_advect_t<DT_F16, MODE_LINEAR>(a, R, s);
-        default: return launch_advect_t<DT_BF16, MODE_LINEAR>(a, R, s);
-        }
-    }
     switch (dtype) {
-    case DT_F32: return launch_advect_t<DT_F32, MODE_FROZEN>(a, R, s);
-    case DT_F16: return launch_advect_t<DT_F16, MODE_FROZEN>(a, R, s);
-    default: return launch_advect_t<DT_BF16, MODE_FROZEN>(a, R, s);
+    case DT_F32: return launch_advect_m<DT_F32>(a, mode, R, s);
+    case DT_F16: return launch_advect_m<DT_F16>(a, mode, R, s);
+    default: return launch_advect_m<DT_BF16>(a, mode, R, s);
     }
 }
 
 template <int DT, int MODE>
-static int occ() {
+static int occ_t() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, advect_kernel<DT, MODE>, BLOCK, 0) != hipSuccess)
-        return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, advect_kernel<DT, MODE>, BLOCK, 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
+template <int DT>
+static int occ_m(int mode) {
+    return mode == MODE_LINEAR ? occ_t<DT, MODE_LINEAR>() : occ_t<DT, MODE_FROZEN>();
+}
+
 int advect_max_blocks_per_cu(int dtype, int mode) {
-    if (mode == MODE_LINEAR)
-        return dtype == DT_F32 ? occ<DT_F32, MODE_LINEAR>() : dtype == DT_F16 ? occ<DT_F16, MODE_LINEAR>()
-                                                                              : occ<DT_BF16, MODE_LINEAR>();
-    return dtype == DT_F32 ? occ<DT_F32, MODE_FROZEN>() : dtype == DT_F16 ? occ<DT_F16, MODE_FROZEN>()
-                                                                          : occ<DT_BF16, MODE_FROZEN>();
+    switch (dtype) {
+    case DT_F32: return occ_m<DT_F32>(mode);
+    case DT_F16: return occ_m<DT_F16>(mode);
+    default: return occ_m<DT_BF16>(mode);
+    }
 }
 
 hipError_t launch_flowmap(const FlowmapArgs& a, int R, hipStream_t s) {

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -22,6 +23,7 @@ struct bto_ctx {
     int device = 0;
     int64_t cap = 0;
     int cus_per_xcd = 32;
+    int steps_per_launch = KMAX;  // fused steps per advect launch (BTO_STEPS_PER_LAUNCH)
     // particle state (ping-pong)
     PState* pos[2] = {nullptr, nullptr};
     uint32_t* id[2] = {nullptr, nullptr};
@@ -30,7 +32,7 @@ struct bto_ctx {
     PState* rec_pos = nullptr;
     int32_t* rec_meta = nullptr;
     double* seed_xyz = nullptr;
-    // counters: ring of 3 x NSEG live counts, then the particle-step total
+    // counters: ring of 3 x NSEG live counts, then NSEG particle-step counters
     uint32_t* counts = nullptr;
     unsigned long long* psteps = nullptr;
     int slot = 0;           // ring slot holding the current live counts
@@ -107,11 +109,15 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
         c->geom.nmax[d] = (double)(blk->n[d] - 1);
         c->geom.inv_sp[d] = 1.0 / blk->spacing[d];
     }
-    c->geom.sy = (uint64_t)blk->n[0];
-    c->geom.sz = (uint64_t)blk->n[0] * (uint64_t)blk->n[1];
+    c->geom.sy = (uint32_t)blk->n[0];
+    c->geom.sz = (uint32_t)blk->n[0] * (uint32_t)blk->n[1];
     if (hipSetDevice(device) != hipSuccess) {
         delete c;
         return BTO_EINVAL;
+    }
+    if (const char* e = std::getenv("BTO_STEPS_PER_LAUNCH")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= KMAX) c->steps_per_launch = v;
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount >= NSEG)
@@ -125,7 +131,7 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     ok = ok && hipMalloc(&c->rec_pos, P * sizeof(PState)) == hipSuccess;
     ok = ok && hipMalloc(&c->rec_meta, P * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(&c->seed_xyz, P * 3 * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&c->counts, 3 * NSEG * sizeof(uint32_t) + 64) == hipSuccess;
+    ok = ok && hipMalloc(&c->counts, 3 * NSEG * sizeof(uint32_t) + 32 + NSEG * sizeof(unsigned long long)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         bto_destroy(c);
@@ -270,8 +276,8 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
     const int per_cu = advect_max_blocks_per_cu(dtype, flags);
     const int R = blocks_per_seg(c, max_seg, per_cu);
-    // launches of (nearly) equal length, at most KMAX steps each
-    const int nl = (n_steps + KMAX - 1) / KMAX;
+    // launches of (nearly) equal length, at most steps_per_launch steps each
+    const int nl = (n_steps + c->steps_per_launch - 1) / c->steps_per_launch;
     for (int32_t l = 0, q0 = 0; l < nl; ++l) {
         const int K = n_steps / nl + (l < n_steps % nl ? 1 : 0);
         AdvectArgs a{};
@@ -351,13 +357,15 @@ int bto_stats(bto_ctx* c, bto_stats_t* out, void* stream) {
     if (!c->seeded) return BTO_OK;
     hipStream_t s = (hipStream_t)stream;
     uint32_t cnt[NSEG];
-    unsigned long long ps = 0;
+    unsigned long long psv[NSEG];
     hipError_t e = hipMemcpyAsync(cnt, c->counts + NSEG * c->slot, sizeof cnt, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&ps, c->psteps, sizeof ps, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(psv, c->psteps, sizeof psv, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "stats readback");
     int64_t live = 0;
     for (int x = 0; x < NSEG; ++x) live += cnt[x];
+    unsigned long long ps = 0;
+    for (int x = 0; x < NSEG; ++x) ps += psv[x];
     out->n_live = live;
     out->particle_steps = (int64_t)ps;
     return BTO_OK;

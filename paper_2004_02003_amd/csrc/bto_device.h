@@ -9,9 +9,9 @@
 //
 // Velocity grids stay in the caller's layout (AoS xyz per point, x fastest).
 // The sampler reads each cell as four x-rows of two adjacent points (24 bytes
-// for float32, 12 bytes for float16/bfloat16), one vector load per row; gfx950
-// under ROCm runs with unaligned global access enabled, so the 2-byte-aligned
-// 12-byte rows of 16-bit grids need no padding.
+// for float32, 12 bytes for float16/bfloat16), one vector access per row;
+// gfx950 under ROCm runs with unaligned global access enabled, so the
+// 2-byte-aligned 12-byte rows of 16-bit grids need no padding.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,48 +55,13 @@ __device__ __forceinline__ PState pack(const double x[3]) {
 }
 
 // ---------------------------------------------------------------------------
-// Velocity rows: two x-adjacent grid points, 6 components.
-// ---------------------------------------------------------------------------
-struct __attribute__((packed, aligned(4))) Row32 { float v[6]; };
-struct __attribute__((packed, aligned(2))) Row16 { uint16_t v[6]; };
-
-template <int DT> struct Field;
-
-template <> struct Field<DT_F32> {
-    static constexpr int BYTES = 12;  // per grid point
-    __device__ __forceinline__ static void row(const char* base, uint64_t pt, float out[6]) {
-        const Row32 r = *reinterpret_cast<const Row32*>(base + pt * 12u);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) out[q] = r.v[q];
-    }
-};
-
-template <> struct Field<DT_F16> {
-    static constexpr int BYTES = 6;
-    __device__ __forceinline__ static void row(const char* base, uint64_t pt, float out[6]) {
-        const Row16 r = *reinterpret_cast<const Row16*>(base + pt * 6u);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) out[q] = (float)__builtin_bit_cast(_Float16, r.v[q]);
-    }
-};
-
-template <> struct Field<DT_BF16> {
-    static constexpr int BYTES = 6;
-    __device__ __forceinline__ static void row(const char* base, uint64_t pt, float out[6]) {
-        const Row16 r = *reinterpret_cast<const Row16*>(base + pt * 6u);
-#pragma unroll
-        for (int q = 0; q < 6; ++q) out[q] = __uint_as_float((uint32_t)r.v[q] << 16);
-    }
-};
-
-// ---------------------------------------------------------------------------
 // Block geometry in cell units.
 // ---------------------------------------------------------------------------
 struct Geom {
     int32_t n[3];        // grid points per axis
     double nmax[3];      // n - 1: the closed box is [0, nmax]
     double inv_sp[3];    // 1 / spacing: world velocity -> cells per unit time
-    uint64_t sy, sz;     // point strides of y and z
+    uint32_t sy, sz;     // point strides of y and z (n <= 1024 per axis)
 };
 
 __device__ __forceinline__ bool inside(const Geom& g, const double p[3]) {
@@ -106,7 +71,7 @@ __device__ __forceinline__ bool inside(const Geom& g, const double p[3]) {
 
 // Sampling cell i_d = min(floor(p_d), n_d - 2) and FP32 offset f_d = p_d - i_d.
 struct Cell {
-    uint64_t base;  // point index of corner (i, j, k)
+    uint32_t base;  // point index of corner (i, j, k)
     float f[3];
 };
 
@@ -120,60 +85,105 @@ __device__ __forceinline__ Cell locate(const Geom& g, const double p[3]) {
         i[d] = v;
         c.f[d] = (float)(p[d] - (double)v);
     }
-    c.base = (uint64_t)i[0] + g.sy * (uint64_t)i[1] + g.sz * (uint64_t)i[2];
+    c.base = (uint32_t)i[0] + g.sy * (uint32_t)i[1] + g.sz * (uint32_t)i[2];
     return c;
 }
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
 
-// Trilinear interpolation of 8 corner values given as 4 x-rows
-// (row r = y-offset (r & 1), z-offset (r >> 1)), component-interleaved.
-__device__ __forceinline__ void trilerp(const float R[4][6], const float f[3], float out[3]) {
+// ---------------------------------------------------------------------------
+// Corner values of one cell of one grid level, held in registers across the
+// RK4 stages (and across steps: the level n+1 corners of step n are the level
+// n corners of step n+1).  Four x-rows of two adjacent points; row r has
+// y-offset (r & 1) and z-offset (r >> 1); value (r, q) is component q % 3 of
+// point q / 3.  32-bit grids keep FP32 values; 16-bit grids keep the raw
+// halves (3 dwords per row) and convert when read.
+// ---------------------------------------------------------------------------
+constexpr uint32_t NO_CELL = 0xFFFFFFFFu;
+
+struct __attribute__((packed, aligned(4))) Row32 { float v[6]; };
+struct __attribute__((packed, aligned(2))) Row16 { uint32_t w[3]; };
+
+template <int DT> struct CellCache;
+
+template <> struct CellCache<DT_F32> {
+    uint32_t base;
+    float R[4][6];
+    __device__ __forceinline__ float v(int r, int q) const { return R[r][q]; }
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
+        const Row32 x = *reinterpret_cast<const Row32*>(V + (uint64_t)pt * 12u);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) R[r][q] = x.v[q];
+    }
+};
+
+template <> struct CellCache<DT_F16> {
+    uint32_t base;
+    uint32_t P[4][3];
+    __device__ __forceinline__ float v(int r, int q) const {
+        const uint16_t h = (uint16_t)(P[r][q >> 1] >> ((q & 1) * 16));
+        return (float)__builtin_bit_cast(_Float16, h);
+    }
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
+        const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
+        P[r][0] = x.w[0];
+        P[r][1] = x.w[1];
+        P[r][2] = x.w[2];
+    }
+};
+
+template <> struct CellCache<DT_BF16> {
+    uint32_t base;
+    uint32_t P[4][3];
+    __device__ __forceinline__ float v(int r, int q) const {
+        const uint32_t w = P[r][q >> 1];
+        return __uint_as_float((q & 1) ? (w & 0xFFFF0000u) : (w << 16));
+    }
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
+        const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
+        P[r][0] = x.w[0];
+        P[r][1] = x.w[1];
+        P[r][2] = x.w[2];
+    }
+};
+
+template <int DT>
+__device__ __forceinline__ void ensure(const Geom& g, const char* V, uint32_t base, CellCache<DT>& c) {
+    if (c.base != base) {
+        c.load_row(V, base, 0);
+        c.load_row(V, base + g.sy, 1);
+        c.load_row(V, base + g.sz, 2);
+        c.load_row(V, base + g.sy + g.sz, 3);
+        c.base = base;
+    }
+}
+
+// Trilinear interpolation of one level.
+template <class CA>
+__device__ __forceinline__ void trilerp(const CA& A, const float f[3], float out[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float a00 = lerp(R[0][c], R[0][3 + c], f[0]);
-        const float a10 = lerp(R[1][c], R[1][3 + c], f[0]);
-        const float a01 = lerp(R[2][c], R[2][3 + c], f[0]);
-        const float a11 = lerp(R[3][c], R[3][3 + c], f[0]);
+        const float a00 = lerp(A.v(0, c), A.v(0, 3 + c), f[0]);
+        const float a10 = lerp(A.v(1, c), A.v(1, 3 + c), f[0]);
+        const float a01 = lerp(A.v(2, c), A.v(2, 3 + c), f[0]);
+        const float a11 = lerp(A.v(3, c), A.v(3, 3 + c), f[0]);
         const float b0 = lerp(a00, a10, f[1]);
         const float b1 = lerp(a01, a11, f[1]);
         out[c] = lerp(b0, b1, f[2]);
     }
 }
 
-__device__ __forceinline__ bool finite3(const float k[3]) {
-    return __builtin_isfinite(k[0]) && __builtin_isfinite(k[1]) && __builtin_isfinite(k[2]);
-}
-
-// Corner values of one cell of one grid level, held in registers across the
-// RK4 stages (and across steps: the level n+1 rows of step n are the level n
-// rows of step n+1).  A stage only reloads when its point lies in another cell.
-struct CellCache {
-    uint64_t base;  // point index of the cached cell's corner (i, j, k); ~0 = empty
-    float R[4][6];
-};
-
-template <int DT>
-__device__ __forceinline__ void ensure(const Geom& g, const char* V, uint64_t base, CellCache& c) {
-    if (c.base != base) {
-        Field<DT>::row(V, base, c.R[0]);
-        Field<DT>::row(V, base + g.sy, c.R[1]);
-        Field<DT>::row(V, base + g.sz, c.R[2]);
-        Field<DT>::row(V, base + g.sy + g.sz, c.R[3]);
-        c.base = base;
-    }
-}
-
-// trilinear interpolation of the time midpoint (A + B) / 2 of two levels
-__device__ __forceinline__ void trilerp_mid(const float A[4][6], const float B[4][6], const float f[3],
-                                            float out[3]) {
+// Trilinear interpolation of the time midpoint (A + B) / 2 of two levels
+// (interpolation is linear in the grid values, so corners are averaged first).
+template <class CA>
+__device__ __forceinline__ void trilerp_mid(const CA& A, const CA& B, const float f[3], float out[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         float a[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float lo = 0.5f * (A[r][c] + B[r][c]);
-            const float hi = 0.5f * (A[r][3 + c] + B[r][3 + c]);
+            const float lo = 0.5f * (A.v(r, c) + B.v(r, c));
+            const float hi = 0.5f * (A.v(r, 3 + c) + B.v(r, 3 + c));
             a[r] = lerp(lo, hi, f[0]);
         }
         const float b0 = lerp(a[0], a[1], f[1]);
@@ -183,18 +193,18 @@ __device__ __forceinline__ void trilerp_mid(const float A[4][6], const float B[4
 }
 
 // Trilinear value and its derivatives with respect to the in-cell offset
-// (d v_c / d f_d, which equals d v_c / d p_d in cell units) from the 8 corner
-// values; `mid` averages two levels per corner first (time midpoint).
-template <bool MID>
-__device__ __forceinline__ void trilerp_grad(const float A[4][6], const float B[4][6], const float f[3],
-                                             float v[3], float G[3][3]) {
+// (d v_c / d f_d, which equals d v_c / d p_d in cell units); MID averages the
+// two levels per corner first (time midpoint).
+template <bool MID, class CA>
+__device__ __forceinline__ void trilerp_grad(const CA& A, const CA& B, const float f[3], float v[3],
+                                             float G[3][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         float lo[4], hi[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            lo[r] = MID ? 0.5f * (A[r][c] + B[r][c]) : A[r][c];
-            hi[r] = MID ? 0.5f * (A[r][3 + c] + B[r][3 + c]) : A[r][3 + c];
+            lo[r] = MID ? 0.5f * (A.v(r, c) + B.v(r, c)) : A.v(r, c);
+            hi[r] = MID ? 0.5f * (A.v(r, 3 + c) + B.v(r, 3 + c)) : A.v(r, 3 + c);
         }
         float a[4], dx[4];
 #pragma unroll
@@ -211,16 +221,22 @@ __device__ __forceinline__ void trilerp_grad(const float A[4][6], const float B[
     }
 }
 
+__device__ __forceinline__ bool finite3(const float k[3]) {
+    return __builtin_isfinite(k[0]) && __builtin_isfinite(k[1]) && __builtin_isfinite(k[2]);
+}
+
 // Per-lane stepping state: FP64 position plus the two cached levels.
+template <int DT>
 struct Stepper {
     double x[3];
-    CellCache A;  // level n   (cycle of the step's start)
-    CellCache B;  // level n+1
+    CellCache<DT> A;  // level n   (cycle of the step's start)
+    CellCache<DT> B;  // level n+1
 };
 
-__device__ __forceinline__ void stepper_init(Stepper& st) {
-    st.A.base = ~0ull;
-    st.B.base = ~0ull;
+template <int DT>
+__device__ __forceinline__ void stepper_init(Stepper<DT>& st) {
+    st.A.base = NO_CELL;
+    st.B.base = NO_CELL;
 }
 
 // One classic RK4 step of one cycle: stage times t, t+h/2, t+h/2, t+h with the
@@ -229,7 +245,7 @@ __device__ __forceinline__ void stepper_init(Stepper& st) {
 // each later stage point and the end point are checked inside the block, in
 // order.  On any event x is left at the step's start.
 template <int DT, int MODE>
-__device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, Stepper& st) {
+__device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, Stepper<DT>& st) {
     const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
     float k1[3], k2[3], k3[3], k4[3];
     double y[3];
@@ -238,7 +254,7 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
 
     c = locate(g, x);
     ensure<DT>(g, V0, c.base, st.A);
-    trilerp(st.A.R, c.f, k1);
+    trilerp(st.A, c.f, k1);
     if (!finite3(k1)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = fma(0.5 * hs[d], (double)k1[d], x[d]);
@@ -248,9 +264,9 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     ensure<DT>(g, V0, c.base, st.A);
     if (MODE == MODE_LINEAR) {
         ensure<DT>(g, V1, c.base, st.B);
-        trilerp_mid(st.A.R, st.B.R, c.f, k2);
+        trilerp_mid(st.A, st.B, c.f, k2);
     } else {
-        trilerp(st.A.R, c.f, k2);
+        trilerp(st.A, c.f, k2);
     }
     if (!finite3(k2)) return S_INVALID;
 #pragma unroll
@@ -261,9 +277,9 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     ensure<DT>(g, V0, c.base, st.A);
     if (MODE == MODE_LINEAR) {
         ensure<DT>(g, V1, c.base, st.B);
-        trilerp_mid(st.A.R, st.B.R, c.f, k3);
+        trilerp_mid(st.A, st.B, c.f, k3);
     } else {
-        trilerp(st.A.R, c.f, k3);
+        trilerp(st.A, c.f, k3);
     }
     if (!finite3(k3)) return S_INVALID;
 #pragma unroll
@@ -273,10 +289,10 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     c = locate(g, y);
     if (MODE == MODE_LINEAR) {
         ensure<DT>(g, V1, c.base, st.B);
-        trilerp(st.B.R, c.f, k4);
+        trilerp(st.B, c.f, k4);
     } else {
         ensure<DT>(g, V0, c.base, st.A);
-        trilerp(st.A.R, c.f, k4);
+        trilerp(st.A, c.f, k4);
     }
     if (!finite3(k4)) return S_INVALID;
 #pragma unroll
@@ -292,14 +308,14 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
 }
 
 // After a step the level n+1 rows serve as the next step's level n rows.
-template <int MODE>
-__device__ __forceinline__ void stepper_next_cycle(Stepper& st) {
+template <int MODE, int DT>
+__device__ __forceinline__ void stepper_next_cycle(Stepper<DT>& st) {
     if (MODE == MODE_LINEAR) {
         st.A = st.B;
     } else {
-        st.A.base = ~0ull;
+        st.A.base = NO_CELL;
     }
-    st.B.base = ~0ull;
+    st.B.base = NO_CELL;
 }
 
 }  // namespace bto

@@ -32,7 +32,7 @@ struct AdvectArgs {
     uint32_t* clear_count;      // NSEG counts cleared for the launch after next
     PState* rec_pos;            // per seed id: final state of ended particles
     int32_t* rec_meta;          // per seed id: flag << 28 | exit step
-    unsigned long long* psteps; // attempted particle-steps
+    unsigned long long* psteps; // NSEG counters of attempted particle-steps
 };
 
 struct SeedLatticeArgs {
