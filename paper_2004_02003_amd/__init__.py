@@ -17,6 +17,9 @@ def __getattr__(name):
     if name in ("Context", "grid_to_device"):
         from . import context
         return getattr(context, name)
+    if name == "InSituDriver":
+        from . import insitu
+        return insitu.InSituDriver
     if name in ("BTOAdvectFn", "advect_autograd", "jacobian_ftle"):
         from . import autograd
         return getattr(autograd, name)

@@ -24,6 +24,7 @@ struct bto_ctx {
     int64_t cap = 0;
     int cus_per_xcd = 32;
     int steps_per_launch = KMAX;  // fused steps per advect launch (BTO_STEPS_PER_LAUNCH)
+    int blocks_per_cu_cap = 0;    // cap on resident advect workgroups per CU (BTO_BLOCKS_PER_CU; 0 = occupancy)
     // particle state (ping-pong)
     PState* pos[2] = {nullptr, nullptr};
     uint32_t* id[2] = {nullptr, nullptr};
@@ -119,6 +120,7 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
         const int v = std::atoi(e);
         if (v >= 1 && v <= KMAX) c->steps_per_launch = v;
     }
+    if (const char* e = std::getenv("BTO_BLOCKS_PER_CU")) c->blocks_per_cu_cap = std::atoi(e);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount >= NSEG)
         c->cus_per_xcd = prop.multiProcessorCount / NSEG;
@@ -274,7 +276,8 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     }
     int64_t max_seg = 0;
     for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
-    const int per_cu = advect_max_blocks_per_cu(dtype, flags);
+    int per_cu = advect_max_blocks_per_cu(dtype, flags);
+    if (c->blocks_per_cu_cap > 0 && c->blocks_per_cu_cap < per_cu) per_cu = c->blocks_per_cu_cap;
     const int R = blocks_per_seg(c, max_seg, per_cu);
     // launches of (nearly) equal length, at most steps_per_launch steps each
     const int nl = (n_steps + c->steps_per_launch - 1) / c->steps_per_launch;

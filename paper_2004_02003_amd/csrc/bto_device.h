@@ -96,54 +96,35 @@ __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t
 // RK4 stages (and across steps: the level n+1 corners of step n are the level
 // n corners of step n+1).  Four x-rows of two adjacent points; row r has
 // y-offset (r & 1) and z-offset (r >> 1); value (r, q) is component q % 3 of
-// point q / 3.  32-bit grids keep FP32 values; 16-bit grids keep the raw
-// halves (3 dwords per row) and convert when read.
+// point q / 3.  16-bit grids are converted to FP32 once, when loaded.
 // ---------------------------------------------------------------------------
 constexpr uint32_t NO_CELL = 0xFFFFFFFFu;
 
 struct __attribute__((packed, aligned(4))) Row32 { float v[6]; };
 struct __attribute__((packed, aligned(2))) Row16 { uint32_t w[3]; };
 
-template <int DT> struct CellCache;
-
-template <> struct CellCache<DT_F32> {
+template <int DT>
+struct CellCache {
     uint32_t base;
     float R[4][6];
     __device__ __forceinline__ float v(int r, int q) const { return R[r][q]; }
     __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
-        const Row32 x = *reinterpret_cast<const Row32*>(V + (uint64_t)pt * 12u);
+        if constexpr (DT == DT_F32) {
+            const Row32 x = *reinterpret_cast<const Row32*>(V + (uint64_t)pt * 12u);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) R[r][q] = x.v[q];
-    }
-};
-
-template <> struct CellCache<DT_F16> {
-    uint32_t base;
-    uint32_t P[4][3];
-    __device__ __forceinline__ float v(int r, int q) const {
-        const uint16_t h = (uint16_t)(P[r][q >> 1] >> ((q & 1) * 16));
-        return (float)__builtin_bit_cast(_Float16, h);
-    }
-    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
-        const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
-        P[r][0] = x.w[0];
-        P[r][1] = x.w[1];
-        P[r][2] = x.w[2];
-    }
-};
-
-template <> struct CellCache<DT_BF16> {
-    uint32_t base;
-    uint32_t P[4][3];
-    __device__ __forceinline__ float v(int r, int q) const {
-        const uint32_t w = P[r][q >> 1];
-        return __uint_as_float((q & 1) ? (w & 0xFFFF0000u) : (w << 16));
-    }
-    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
-        const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
-        P[r][0] = x.w[0];
-        P[r][1] = x.w[1];
-        P[r][2] = x.w[2];
+            for (int q = 0; q < 6; ++q) R[r][q] = x.v[q];
+        } else {
+            const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const uint32_t w = x.w[q >> 1];
+                if constexpr (DT == DT_F16) {
+                    R[r][q] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> ((q & 1) * 16)));
+                } else {
+                    R[r][q] = __uint_as_float((q & 1) ? (w & 0xFFFF0000u) : (w << 16));
+                }
+            }
+        }
     }
 };
 
@@ -158,37 +139,53 @@ __device__ __forceinline__ void ensure(const Geom& g, const char* V, uint32_t ba
     }
 }
 
-// Trilinear interpolation of one level.
-template <class CA>
-__device__ __forceinline__ void trilerp(const CA& A, const float f[3], float out[3]) {
+// Trilinear corner weights w[r][x] (row r as above, x-offset x), times `scale`.
+__device__ __forceinline__ void corner_weights(const float f[3], float scale, float w[4][2]) {
+    const float wz0 = (1.f - f[2]) * scale, wz1 = f[2] * scale;
+    const float wy0 = 1.f - f[1], wy1 = f[1];
+    const float yz[4] = {wy0 * wz0, wy1 * wz0, wy0 * wz1, wy1 * wz1};
+    const float wx0 = 1.f - f[0], wx1 = f[0];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const float a00 = lerp(A.v(0, c), A.v(0, 3 + c), f[0]);
-        const float a10 = lerp(A.v(1, c), A.v(1, 3 + c), f[0]);
-        const float a01 = lerp(A.v(2, c), A.v(2, 3 + c), f[0]);
-        const float a11 = lerp(A.v(3, c), A.v(3, 3 + c), f[0]);
-        const float b0 = lerp(a00, a10, f[1]);
-        const float b1 = lerp(a01, a11, f[1]);
-        out[c] = lerp(b0, b1, f[2]);
+    for (int r = 0; r < 4; ++r) {
+        w[r][0] = yz[r] * wx0;
+        w[r][1] = yz[r] * wx1;
     }
 }
 
-// Trilinear interpolation of the time midpoint (A + B) / 2 of two levels
-// (interpolation is linear in the grid values, so corners are averaged first).
+// Trilinear interpolation of one level.
 template <class CA>
-__device__ __forceinline__ void trilerp_mid(const CA& A, const CA& B, const float f[3], float out[3]) {
+__device__ __forceinline__ void trilerp(const CA& A, const float f[3], float out[3]) {
+    float w[4][2];
+    corner_weights(f, 1.f, w);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float a[4];
+        float acc = w[0][0] * A.v(0, c);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float lo = 0.5f * (A.v(r, c) + B.v(r, c));
-            const float hi = 0.5f * (A.v(r, 3 + c) + B.v(r, 3 + c));
-            a[r] = lerp(lo, hi, f[0]);
+            if (r) acc = fmaf(w[r][0], A.v(r, c), acc);
+            acc = fmaf(w[r][1], A.v(r, 3 + c), acc);
         }
-        const float b0 = lerp(a[0], a[1], f[1]);
-        const float b1 = lerp(a[2], a[3], f[1]);
-        out[c] = lerp(b0, b1, f[2]);
+        out[c] = acc;
+    }
+}
+
+// Trilinear interpolation of the time midpoint (A + B) / 2 of two levels:
+// the factor 1/2 is folded into the weights.
+template <class CA>
+__device__ __forceinline__ void trilerp_mid(const CA& A, const CA& B, const float f[3], float out[3]) {
+    float w[4][2];
+    corner_weights(f, 0.5f, w);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float acc = w[0][0] * A.v(0, c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r) acc = fmaf(w[r][0], A.v(r, c), acc);
+            acc = fmaf(w[r][0], B.v(r, c), acc);
+            acc = fmaf(w[r][1], A.v(r, 3 + c), acc);
+            acc = fmaf(w[r][1], B.v(r, 3 + c), acc);
+        }
+        out[c] = acc;
     }
 }
 
