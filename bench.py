@@ -100,8 +100,19 @@ def main(argv=None):
     log(f"workload {wl.name}: generating {wl.n_cycles} grids {wl.n} ({dt})")
     t0 = time.time()
     series = wl.make_field()
-    grids_host = series.grids(dt) if (not args.no_cpu_baseline or not args.no_variants) else None
-    dev = [grid_to_device(g, dt) for g in (grids_host if grids_host is not None else series.grids(dt))]
+    turb = series.lazy is not None
+    if turb:
+        # large turbulence blocks: grids generated on the device (bit-identical to the host evaluator)
+        from bto_inputs import _turb
+        gen = _turb.DeviceTurbulence(series.lazy)
+        tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dt]
+        shape = (wl.n[2], wl.n[1], wl.n[0], 3)
+        dev = [gen.fill(c, dt, torch.empty(shape, dtype=tdt, device="cuda")) for c in range(wl.n_cycles)]
+        grids_host = None
+        args.no_variants = True
+    else:
+        grids_host = series.grids(dt) if (not args.no_cpu_baseline or not args.no_variants) else None
+        dev = [grid_to_device(g, dt) for g in (grids_host if grids_host is not None else series.grids(dt))]
     torch.cuda.synchronize()
     log(f"grids resident ({sum(g.numel() * g.element_size() for g in dev) / 2**30:.2f} GiB) in {time.time() - t0:.1f}s")
     times = np.asarray(series.times, dtype=np.float64)
@@ -174,7 +185,8 @@ def main(argv=None):
         "metric": METRIC, "value": round(value, 1), "unit": "particle-RK4-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
-        "data": "synthetic (seeded analytic ABC flow + Gaussian noise; no dataset)",
+        "data": ("synthetic (seeded analytic ABC flow + Gaussian noise; no dataset)" if not turb else
+                 "synthetic (seeded divergence-free Fourier-mode turbulence; no dataset)"),
         "config": {"workload": wl.name, "n": list(wl.n), "cycles": wl.n_cycles, "dt": wl.dt,
                    "stride": wl.stride, "seeds": P, "interval_steps": N, "storage": dt,
                    "particle_steps_per_interval": int(psteps_interval), "valid_at_end": int(n_valid)},
@@ -244,10 +256,10 @@ def main(argv=None):
         result["storage_variants"] = variants
 
     if not args.no_cpu_baseline:
-        ids = np.arange(0, P, 4)
+        ids = np.arange(0, P, 4 if not turb else 1024)
         seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        F = oracle.Field(wl.n, grids_host, dtype=dt)
+        F = oracle.Field(wl.n, grids_host, dtype=dt) if not turb else oracle.Field.lazy_turbulence(series, dt)
         log(f"oracle CPU baseline on {len(ids)} seeds, {threads} threads")
         tc = time.perf_counter()
         o = oracle.flowmap(F, times, seeds, N, nthreads=threads)
@@ -255,8 +267,8 @@ def main(argv=None):
         ps = int(np.where(o["flag"] == 0, N, o["exit"] + 1).sum())
         result["cpu_baseline"] = {"value": round(ps / tc, 1), "unit": "particle-RK4-steps/s", "cores": threads,
                                   "kind": "oracle",
-                                  "sample": f"every 4th seed of {wl.name} ({len(ids)} seeds x {N} steps, "
-                                            f"{ps} particle-steps, {tc:.1f} s), FP64, OpenMP"}
+                                  "sample": f"every {ids[1] - ids[0]}th seed of {wl.name} ({len(ids)} seeds x {N} "
+                                            f"steps, {ps} particle-steps, {tc:.1f} s), FP64, OpenMP"}
 
     if args.copy_probe:
         x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
