@@ -50,6 +50,9 @@ def field_bytes_per_point(dt: str) -> int:
 
 def launch_plan(n_steps: int, kmax: int = 32):
     kmax = int(os.environ.get("BTO_STEPS_PER_LAUNCH", kmax))
+    rb = int(os.environ.get("BTO_REBIN_EVERY", "0"))
+    if 0 < rb < kmax:
+        kmax = rb
     nl = (n_steps + kmax - 1) // kmax
     return [n_steps // nl + (1 if l < n_steps % nl else 0) for l in range(nl)]
 

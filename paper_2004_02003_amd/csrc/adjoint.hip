@@ -120,8 +120,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) ck[3 * (n / K) + d] = st.x[d];
         }
-        status = rk4_step<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], st);
-        if (status == S_VALID) stepper_next_cycle<MODE>(st);
+        status = rk4_step_alt<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], n, st);
     }
     if (a.status_out) a.status_out[p] = (uint8_t)status;
 
@@ -142,10 +141,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
             for (int n = n0; n < n1; ++n) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) buf[3 * (n - n0) + d] = st.x[d];
-                if (n + 1 < n1) {
-                    rk4_step<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], st);
-                    stepper_next_cycle<MODE>(st);
-                }
+                if (n + 1 < n1) rk4_step_alt<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], n - n0, st);
             }
             for (int n = n1 - 1; n >= n0; --n) {
                 Stepper<DT> sr;

@@ -106,10 +106,17 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
             id = a.in_id[sbase + i];
             unpack(ps, stp.x);
             stepper_init(stp);
+            // two steps per iteration: the slots swap roles, so nothing is copied
             for (s = 0; s < a.K; ++s) {
-                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], stp);
+                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], stp.x, stp.A, stp.B);
                 if (status != S_VALID) break;
-                stepper_next_cycle<MODE>(stp);
+                stp.A.base = NO_CELL;
+                if (MODE != MODE_LINEAR) stp.B.base = NO_CELL;
+                if (++s >= a.K) break;
+                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], stp.x, stp.B, stp.A);
+                if (status != S_VALID) break;
+                stp.B.base = NO_CELL;
+                if (MODE != MODE_LINEAR) stp.A.base = NO_CELL;
             }
             my_steps += (status == S_VALID) ? (uint32_t)a.K : (uint32_t)(s + 1);
         }

@@ -25,6 +25,11 @@ struct bto_ctx {
     int cus_per_xcd = 32;
     int steps_per_launch = KMAX;  // fused steps per advect launch (BTO_STEPS_PER_LAUNCH)
     int blocks_per_cu_cap = 0;    // cap on resident advect workgroups per CU (BTO_BLOCKS_PER_CU; 0 = occupancy)
+    int rebin_every = 0;          // re-sort live particles every this many steps (BTO_REBIN_EVERY; 0 = never)
+    int steps_since_rebin = 0;
+    uint32_t* rebin_buf = nullptr;  // 4 x cap keys/values
+    void* rebin_temp = nullptr;
+    size_t rebin_temp_bytes = 0;
     // particle state (ping-pong)
     PState* pos[2] = {nullptr, nullptr};
     uint32_t* id[2] = {nullptr, nullptr};
@@ -121,6 +126,7 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
         if (v >= 1 && v <= KMAX) c->steps_per_launch = v;
     }
     if (const char* e = std::getenv("BTO_BLOCKS_PER_CU")) c->blocks_per_cu_cap = std::atoi(e);
+    if (const char* e = std::getenv("BTO_REBIN_EVERY")) c->rebin_every = std::atoi(e) > 0 ? std::atoi(e) : 0;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount >= NSEG)
         c->cus_per_xcd = prop.multiProcessorCount / NSEG;
@@ -158,6 +164,8 @@ int bto_destroy(bto_ctx* c) {
     if (c->seed_xyz) (void)hipFree(c->seed_xyz);
     if (c->counts) (void)hipFree(c->counts);
     if (c->adj_scratch) (void)hipFree(c->adj_scratch);
+    if (c->rebin_buf) (void)hipFree(c->rebin_buf);
+    if (c->rebin_temp) (void)hipFree(c->rebin_temp);
     delete c;
     return BTO_OK;
 }
@@ -183,6 +191,49 @@ static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hip
     c->seeded = true;
     c->n_seeds = P;
     c->steps_done = 0;
+    c->steps_since_rebin = 0;
+    return BTO_OK;
+}
+
+// Re-sort the live particles of every segment by brick (Morton) order.
+static int rebin(bto_ctx* c, hipStream_t s) {
+    int bits = 1;
+    for (int d = 0; d < 3; ++d)
+        while ((1 << bits) < (c->blk.n[d] + 7) / 8) ++bits;
+    const uint32_t nbins = 1u << (3 * bits);
+    if (!c->rebin_buf) {
+        const size_t tb = rebin_temp_bytes((int64_t)NSEG * nbins);
+        if (tb == 0) return fail(c, BTO_EHIP, "rebin: scan storage query failed");
+        const size_t words = (size_t)c->cap * 2 + (size_t)NSEG * nbins * 2;
+        if (hipMalloc(&c->rebin_buf, words * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&c->rebin_temp, tb) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, BTO_ENOMEM, "rebin buffers");
+        }
+        // the bin counts start at zero once; each rebin leaves them zero again
+        if (hipMemset(c->rebin_buf + (size_t)c->cap * 2, 0, (size_t)NSEG * nbins * sizeof(uint32_t)) != hipSuccess)
+            return fail(c, BTO_EHIP, "rebin: clearing bin counts failed");
+        c->rebin_temp_bytes = tb;
+    }
+    RebinArgs a{};
+    a.P = c->n_seeds;
+    a.segs = c->segs;
+    a.count = c->counts + NSEG * c->slot;
+    a.pos = c->pos[c->cur];
+    a.id = c->id[c->cur];
+    a.out_pos = c->pos[1 - c->cur];
+    a.out_id = c->id[1 - c->cur];
+    a.bin = c->rebin_buf;
+    a.rank = c->rebin_buf + c->cap;
+    a.hist = c->rebin_buf + 2 * (size_t)c->cap;
+    a.offs = a.hist + (size_t)NSEG * nbins;
+    a.nbins = nbins;
+    a.temp = c->rebin_temp;
+    a.temp_bytes = c->rebin_temp_bytes;
+    hipError_t e = launch_rebin(a, s);
+    if (e != hipSuccess) return hip_fail(c, e, "rebin");
+    c->cur = 1 - c->cur;
+    c->steps_since_rebin = 0;
     return BTO_OK;
 }
 
@@ -280,9 +331,15 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     if (c->blocks_per_cu_cap > 0 && c->blocks_per_cu_cap < per_cu) per_cu = c->blocks_per_cu_cap;
     const int R = blocks_per_seg(c, max_seg, per_cu);
     // launches of (nearly) equal length, at most steps_per_launch steps each
-    const int nl = (n_steps + c->steps_per_launch - 1) / c->steps_per_launch;
+    int kmax = c->steps_per_launch;
+    if (c->rebin_every > 0 && c->rebin_every < kmax) kmax = c->rebin_every;
+    const int nl = (n_steps + kmax - 1) / kmax;
     for (int32_t l = 0, q0 = 0; l < nl; ++l) {
         const int K = n_steps / nl + (l < n_steps % nl ? 1 : 0);
+        if (c->rebin_every > 0 && c->steps_since_rebin >= c->rebin_every) {
+            rc = rebin(c, s);
+            if (rc) return rc;
+        }
         AdvectArgs a{};
         for (int q = 0; q <= K; ++q) a.f[q] = static_cast<const char*>(d_fields[q0 + q]);
         for (int q = 0; q < K; ++q) a.h[q] = times[q0 + q + 1] - times[q0 + q];
@@ -305,6 +362,7 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
         c->cur = 1 - c->cur;
         c->slot = (c->slot + 1) % 3;
         c->steps_done += K;
+        c->steps_since_rebin += K;
         q0 += K;
     }
     return BTO_OK;

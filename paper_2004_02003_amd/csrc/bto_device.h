@@ -242,28 +242,28 @@ __device__ __forceinline__ void stepper_init(Stepper<DT>& st) {
 // each later stage point and the end point are checked inside the block, in
 // order.  On any event x is left at the step's start.
 template <int DT, int MODE>
-__device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, Stepper<DT>& st) {
+__device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, double* x,
+                                        CellCache<DT>& LA, CellCache<DT>& LB) {
     const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
     float k1[3], k2[3], k3[3], k4[3];
     double y[3];
-    double* x = st.x;
     Cell c;
 
     c = locate(g, x);
-    ensure<DT>(g, V0, c.base, st.A);
-    trilerp(st.A, c.f, k1);
+    ensure<DT>(g, V0, c.base, LA);
+    trilerp(LA, c.f, k1);
     if (!finite3(k1)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = fma(0.5 * hs[d], (double)k1[d], x[d]);
     if (!inside(g, y)) return S_TERMINATED;
 
     c = locate(g, y);
-    ensure<DT>(g, V0, c.base, st.A);
+    ensure<DT>(g, V0, c.base, LA);
     if (MODE == MODE_LINEAR) {
-        ensure<DT>(g, V1, c.base, st.B);
-        trilerp_mid(st.A, st.B, c.f, k2);
+        ensure<DT>(g, V1, c.base, LB);
+        trilerp_mid(LA, LB, c.f, k2);
     } else {
-        trilerp(st.A, c.f, k2);
+        trilerp(LA, c.f, k2);
     }
     if (!finite3(k2)) return S_INVALID;
 #pragma unroll
@@ -271,12 +271,12 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     if (!inside(g, y)) return S_TERMINATED;
 
     c = locate(g, y);
-    ensure<DT>(g, V0, c.base, st.A);
+    ensure<DT>(g, V0, c.base, LA);
     if (MODE == MODE_LINEAR) {
-        ensure<DT>(g, V1, c.base, st.B);
-        trilerp_mid(st.A, st.B, c.f, k3);
+        ensure<DT>(g, V1, c.base, LB);
+        trilerp_mid(LA, LB, c.f, k3);
     } else {
-        trilerp(st.A, c.f, k3);
+        trilerp(LA, c.f, k3);
     }
     if (!finite3(k3)) return S_INVALID;
 #pragma unroll
@@ -285,11 +285,11 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
 
     c = locate(g, y);
     if (MODE == MODE_LINEAR) {
-        ensure<DT>(g, V1, c.base, st.B);
-        trilerp(st.B, c.f, k4);
+        ensure<DT>(g, V1, c.base, LB);
+        trilerp(LB, c.f, k4);
     } else {
-        ensure<DT>(g, V0, c.base, st.A);
-        trilerp(st.A, c.f, k4);
+        ensure<DT>(g, V0, c.base, LA);
+        trilerp(LA, c.f, k4);
     }
     if (!finite3(k4)) return S_INVALID;
 #pragma unroll
@@ -304,15 +304,22 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     return S_VALID;
 }
 
-// After a step the level n+1 rows serve as the next step's level n rows.
-template <int MODE, int DT>
-__device__ __forceinline__ void stepper_next_cycle(Stepper<DT>& st) {
-    if (MODE == MODE_LINEAR) {
-        st.A = st.B;
+// Stepping with two cache slots whose roles alternate: step s reads level n
+// from slot s % 2 and level n+1 from the other slot, which then holds the
+// next step's level n, so no corner values are ever copied.
+template <int DT, int MODE>
+__device__ __forceinline__ int rk4_step_alt(const Geom& g, const char* V0, const char* V1, double h, int s,
+                                            Stepper<DT>& st) {
+    int status;
+    if ((s & 1) == 0) {
+        status = rk4_step<DT, MODE>(g, V0, V1, h, st.x, st.A, st.B);
+        if (MODE == MODE_LINEAR) st.A.base = NO_CELL;  // will receive level n+2
     } else {
-        st.A.base = NO_CELL;
+        status = rk4_step<DT, MODE>(g, V0, V1, h, st.x, st.B, st.A);
+        if (MODE == MODE_LINEAR) st.B.base = NO_CELL;
     }
-    st.B.base = NO_CELL;
+    if (MODE != MODE_LINEAR) st.A.base = st.B.base = NO_CELL;
+    return status;
 }
 
 }  // namespace bto

@@ -97,6 +97,23 @@ struct AdjointArgs {
     uint8_t* status_out;        // P (may be null): status of the recomputed forward
 };
 
+struct RebinArgs {
+    int64_t P;                 // slots covered by the segments
+    Segs segs;
+    const uint32_t* count;     // NSEG live counts
+    const PState* pos;         // current buffers
+    const uint32_t* id;
+    PState* out_pos;           // the other ping-pong buffers
+    uint32_t* out_id;
+    uint32_t* bin;             // per slot: (segment, brick) bin
+    uint32_t* rank;            // per slot: rank inside the bin
+    uint32_t* hist;            // NSEG * nbins counts (all zero between rebins)
+    uint32_t* offs;            // NSEG * nbins exclusive prefix sums
+    uint32_t nbins;            // bricks (Morton index range) per segment
+    void* temp;
+    size_t temp_bytes;
+};
+
 hipError_t launch_seed_lattice(const SeedLatticeArgs& a, hipStream_t s);
 hipError_t launch_seed_explicit(const SeedExplicitArgs& a, hipStream_t s);
 hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, unsigned long long* psteps,
@@ -106,5 +123,7 @@ hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t 
 int advect_max_blocks_per_cu(int dtype, int mode);
 hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s);
+size_t rebin_temp_bytes(int64_t nbins_total);
+hipError_t launch_rebin(const RebinArgs& a, hipStream_t s);
 
 }  // namespace bto
