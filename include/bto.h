@@ -129,6 +129,26 @@ int bto_flowmap_out(bto_ctx *ctx, double *d_seed_xyz, double *d_end_xyz, uint8_t
 /* Counters of the current interval.  Synchronizes `stream`. */
 int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
 
+/* Launch-shape tuning of the advection (none of it changes results):
+ *   steps_per_launch  RK4 steps fused into one kernel launch, 1..32
+ *                     (default 32; launches are balanced to equal lengths);
+ *   rebin_every       re-sort the live particles by 8x8x8-cell brick every
+ *                     this many steps (restores cache locality as the flow
+ *                     mixes them; 0 = never, the default);
+ *   blocks_per_cu     cap on resident advection workgroups per compute unit
+ *                     (0 = as many as the register budget allows).
+ * Defaults come from the environment variables BTO_STEPS_PER_LAUNCH,
+ * BTO_REBIN_EVERY and BTO_BLOCKS_PER_CU when the context is created.
+ * BTO_EINVAL for values out of range; takes effect on the next advect call. */
+typedef struct {
+    int32_t steps_per_launch;
+    int32_t rebin_every;
+    int32_t blocks_per_cu;
+} bto_tuning;
+
+int bto_set_tuning(bto_ctx *ctx, const bto_tuning *t);
+int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
+
 /* Discrete adjoint of the interval (gradients for the north-star
  * differentiation workload; FTLE use of the flow map: Results section).
  * For the seeds of the current interval (bto_seed*), recompute the RK4

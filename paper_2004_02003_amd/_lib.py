@@ -20,6 +20,7 @@ BTO_VALID, BTO_TERMINATED, BTO_INVALID = 0, 1, 2
 EXPORTED = [
     "bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
     "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle",
+    "bto_set_tuning", "bto_get_tuning",
 ]
 
 _ERRNAMES = {BTO_EINVAL: "BTO_EINVAL", BTO_ENOMEM: "BTO_ENOMEM", BTO_EHIP: "BTO_EHIP",
@@ -35,6 +36,11 @@ class BTOError(RuntimeError):
 class Block(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3),
                 ("spacing", ctypes.c_double * 3)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("steps_per_launch", ctypes.c_int32), ("rebin_every", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -67,6 +73,8 @@ def load() -> ctypes.CDLL:
     L.bto_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
     L.bto_adjoint_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
     L.bto_ftle.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]
+    L.bto_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.bto_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     for fn in EXPORTED:
         if fn != "bto_last_error":
             getattr(L, fn).restype = ctypes.c_int

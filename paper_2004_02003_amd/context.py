@@ -83,6 +83,21 @@ class Context:
     def handle(self) -> int:
         return self._h.value
 
+    def tuning(self) -> dict:
+        t = _lib.Tuning()
+        self._check(self.L.bto_get_tuning(self._h, ctypes.byref(t)))
+        return dict(steps_per_launch=t.steps_per_launch, rebin_every=t.rebin_every,
+                    blocks_per_cu=t.blocks_per_cu)
+
+    def set_tuning(self, steps_per_launch=None, rebin_every=None, blocks_per_cu=None):
+        """Launch shape of the advection (never changes results)."""
+        cur = self.tuning()
+        t = _lib.Tuning()
+        t.steps_per_launch = cur["steps_per_launch"] if steps_per_launch is None else int(steps_per_launch)
+        t.rebin_every = cur["rebin_every"] if rebin_every is None else int(rebin_every)
+        t.blocks_per_cu = cur["blocks_per_cu"] if blocks_per_cu is None else int(blocks_per_cu)
+        self._check(self.L.bto_set_tuning(self._h, ctypes.byref(t)))
+
     # -- the path ----------------------------------------------------------
     def seed(self, stride: int, offset=None, stream=None) -> int:
         off = None if offset is None else (ctypes.c_double * 3)(*[float(v) for v in offset])

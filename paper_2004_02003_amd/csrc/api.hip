@@ -520,4 +520,25 @@ int bto_ftle(bto_ctx* c, const float* d_jac, int64_t n, double T, float* d_out, 
     return BTO_OK;
 }
 
+int bto_set_tuning(bto_ctx* c, const bto_tuning* t) {
+    if (!c) return BTO_EINVAL;
+    if (!t) return fail(c, BTO_EINVAL, "null tuning");
+    if (t->steps_per_launch < 1 || t->steps_per_launch > KMAX)
+        return fail(c, BTO_EINVAL, "steps_per_launch must be in 1..%d", KMAX);
+    if (t->rebin_every < 0) return fail(c, BTO_EINVAL, "rebin_every must be >= 0");
+    if (t->blocks_per_cu < 0) return fail(c, BTO_EINVAL, "blocks_per_cu must be >= 0");
+    c->steps_per_launch = t->steps_per_launch;
+    c->rebin_every = t->rebin_every;
+    c->blocks_per_cu_cap = t->blocks_per_cu;
+    return BTO_OK;
+}
+
+int bto_get_tuning(const bto_ctx* c, bto_tuning* t) {
+    if (!c || !t) return BTO_EINVAL;
+    t->steps_per_launch = c->steps_per_launch;
+    t->rebin_every = c->rebin_every;
+    t->blocks_per_cu = c->blocks_per_cu_cap;
+    return BTO_OK;
+}
+
 }  // extern "C"

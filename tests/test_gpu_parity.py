@@ -281,3 +281,52 @@ def test_rebin_between_launches_keeps_results():
         assert np.array_equal(r["flag"][~amb], a["flag"][~amb])
         assert np.abs(r["end"] - a["end"]).max() < 5e-6
         assert r["stats"]["particle_steps"] == a["stats"]["particle_steps"] or amb.any()
+
+
+def test_error_paths_and_tuning_through_the_c_abi():
+    """Validation happens before anything is enqueued: out-of-order calls,
+    bad arguments and capacity overflow return the documented codes, the
+    message names the problem, and the context stays usable afterwards."""
+    import torch
+    from paper_2004_02003_amd import BTOError, Context
+    from paper_2004_02003_amd import _lib
+
+    _say("error paths")
+    n = (12, 10, 8)
+    s = fields.uniform_flow(n, [0.2, 0.1, 0.0], np.arange(4) * 0.5)
+    dev = _dev(s.grids("f32"), "f32")
+    with Context(n, 100) as ctx:
+        with pytest.raises(BTOError) as e:
+            ctx.advect(dev, s.times)
+        assert e.value.code == _lib.BTO_ESTATE
+        with pytest.raises(BTOError) as e:
+            ctx.seed(1)  # 12*10*8 = 960 seeds > capacity 100
+        assert e.value.code == _lib.BTO_ERANGE and "capacity" in str(e.value)
+        with pytest.raises(BTOError) as e:
+            ctx.seed(0)
+        assert e.value.code == _lib.BTO_EINVAL
+        P = ctx.seed(3)
+        assert P == 4 * 3 * 3  # offsets 1, 4, 7, (10) on axes of 12, 10, 8 points
+        with pytest.raises(BTOError) as e:
+            ctx.advect(dev, [0.0, 1.0, 1.0, 2.0])
+        assert e.value.code == _lib.BTO_EINVAL and "increasing" in str(e.value)
+        with pytest.raises(BTOError) as e:
+            ctx.advect_ptrs([g.data_ptr() for g in dev], s.times, 7)
+        assert e.value.code == _lib.BTO_EINVAL and "dtype" in str(e.value)
+        with pytest.raises(BTOError) as e:
+            ctx.advect_ptrs([dev[0].data_ptr(), 0], s.times[:2], 0)
+        assert e.value.code == _lib.BTO_EINVAL
+        with pytest.raises(BTOError) as e:
+            ctx.set_tuning(steps_per_launch=0)
+        assert e.value.code == _lib.BTO_EINVAL
+        ctx.set_tuning(steps_per_launch=2, rebin_every=1, blocks_per_cu=1)
+        assert ctx.tuning() == dict(steps_per_launch=2, rebin_every=1, blocks_per_cu=1)
+        ctx.advect(dev, s.times)  # still usable after the failures
+        fm = ctx.flowmap(count_valid=True)
+        torch.cuda.synchronize()
+        assert fm["n_valid"] + int((fm["flag"] != 0).sum()) == P
+        with pytest.raises(BTOError) as e:
+            ctx.adjoint(dev, s.times, torch.zeros((P, 2, 3), dtype=torch.float32, device="cuda"))
+        assert e.value.code == _lib.BTO_EINVAL
+    with pytest.raises(BTOError):
+        Context((1, 4, 4), 10)

@@ -31,7 +31,8 @@ def lib():
 def test_header_declares_the_path_entry_points():
     names = _declared()
     for fn in ("bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
-               "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle"):
+               "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle",
+               "bto_set_tuning", "bto_get_tuning"):
         assert fn in names, fn
 
 
@@ -63,7 +64,10 @@ def test_create_rejects_bad_blocks_before_touching_a_device(lib):
     for fn, args in [("bto_seed", (None, 2, None, None, None)),
                      ("bto_advect_interval", (None, None, None, 1, 0, 0, None)),
                      ("bto_flowmap_out", (None, None, None, None, None, None, None)),
-                     ("bto_stats", (None, None, None))]:
+                     ("bto_stats", (None, None, None)),
+                     ("bto_set_tuning", (None, None)), ("bto_get_tuning", (None, None)),
+                     ("bto_adjoint_interval", (None, None, None, 1, 0, 0, None, 1, None, None, None, 1, None)),
+                     ("bto_ftle", (None, None, 0, 1.0, None, None))]:
         assert getattr(lib, fn)(*args) == _lib.BTO_EINVAL, fn
 
 
