@@ -79,7 +79,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--steps-per-launch", type=int, default=None,
-                    help="RK4 steps fused into one advection launch (1..32; sets BTO_STEPS_PER_LAUNCH)")
+                    help="RK4 steps fused into one advection launch (1..128; sets BTO_STEPS_PER_LAUNCH)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args(argv)

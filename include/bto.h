@@ -130,7 +130,7 @@ int bto_flowmap_out(bto_ctx *ctx, double *d_seed_xyz, double *d_end_xyz, uint8_t
 int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
 
 /* Launch-shape tuning of the advection (none of it changes results):
- *   steps_per_launch  RK4 steps fused into one kernel launch, 1..32
+ *   steps_per_launch  RK4 steps fused into one kernel launch, 1..128
  *                     (default 32; launches are balanced to equal lengths);
  *   rebin_every       re-sort the live particles by 8x8x8-cell brick every
  *                     this many steps (restores cache locality as the flow

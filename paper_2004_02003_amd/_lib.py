@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbto.so")
+# BTO_LIB_PATH may point at another build of the same library (e.g. an
+# instrumented one); there is no fallback when the file is missing.
+LIB_PATH = os.environ.get("BTO_LIB_PATH") or os.path.join(HERE, "libbto.so")
 
 BTO_OK, BTO_EINVAL, BTO_ENOMEM, BTO_EHIP, BTO_ESTATE, BTO_ERANGE = 0, -1, -2, -3, -4, -5
 BTO_F32, BTO_F16, BTO_BF16 = 0, 1, 2

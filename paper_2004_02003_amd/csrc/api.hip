@@ -23,9 +23,10 @@ struct bto_ctx {
     int device = 0;
     int64_t cap = 0;
     int cus_per_xcd = 32;
-    int steps_per_launch = KMAX;  // fused steps per advect launch (BTO_STEPS_PER_LAUNCH)
+    int steps_per_launch = 32;    // fused steps per advect launch, <= KMAX (BTO_STEPS_PER_LAUNCH)
     int blocks_per_cu_cap = 0;    // cap on resident advect workgroups per CU (BTO_BLOCKS_PER_CU; 0 = occupancy)
     int rebin_every = 0;          // re-sort live particles every this many steps (BTO_REBIN_EVERY; 0 = never)
+    int morton_seed = 0;          // Morton brick order at seeding when possible (BTO_MORTON_SEED)
     int steps_since_rebin = 0;
     uint32_t* rebin_buf = nullptr;  // 4 x cap keys/values
     void* rebin_temp = nullptr;
@@ -127,6 +128,7 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     }
     if (const char* e = std::getenv("BTO_BLOCKS_PER_CU")) c->blocks_per_cu_cap = std::atoi(e);
     if (const char* e = std::getenv("BTO_REBIN_EVERY")) c->rebin_every = std::atoi(e) > 0 ? std::atoi(e) : 0;
+    if (const char* e = std::getenv("BTO_MORTON_SEED")) c->morton_seed = std::atoi(e) != 0;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount >= NSEG)
         c->cus_per_xcd = prop.multiProcessorCount / NSEG;
@@ -256,6 +258,12 @@ int bto_seed(bto_ctx* c, int32_t stride, const double* offset3, int64_t* n_seeds
                                 (long long)c->cap);
     a.stride = stride;
     a.P = P;
+    {
+        // Morton brick order needs a cube of 4 * 2^k lattice points per axis (<= 4 * 256)
+        const int32_t mb = a.m[0] / 4;
+        const bool pow2 = mb >= 1 && mb <= 256 && (mb & (mb - 1)) == 0;
+        a.morton = (a.m[0] == a.m[1] && a.m[1] == a.m[2] && a.m[0] % 4 == 0 && pow2 && c->morton_seed) ? 1 : 0;
+    }
     set_segments(c, P);
     a.segs = c->segs;
     a.pos = c->pos[0];

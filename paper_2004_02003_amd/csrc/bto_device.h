@@ -19,7 +19,7 @@
 
 namespace bto {
 
-constexpr int KMAX = 32;   // RK4 steps fused into one launch (one per cycle)
+constexpr int KMAX = 128;  // RK4 steps fused into one launch (one per cycle)
 constexpr int NSEG = 8;    // particle segments, one per XCD
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;

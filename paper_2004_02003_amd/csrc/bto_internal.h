@@ -39,6 +39,7 @@ struct SeedLatticeArgs {
     int32_t m[3];        // lattice points per axis
     double off[3];       // lattice offset (cells)
     int32_t stride;
+    int32_t morton;      // bricks in Morton order (power-of-two cube of bricks)
     int64_t P;
     Segs segs;
     double origin[3], spacing[3];
