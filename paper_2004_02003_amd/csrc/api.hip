@@ -27,6 +27,7 @@ struct bto_ctx {
     int blocks_per_cu_cap = 0;    // cap on resident advect workgroups per CU (BTO_BLOCKS_PER_CU; 0 = occupancy)
     int rebin_every = 0;          // re-sort live particles every this many steps (BTO_REBIN_EVERY; 0 = never)
     int morton_seed = 0;          // Morton brick order at seeding when possible (BTO_MORTON_SEED)
+    int brick[3] = {64, 1, 1};    // lattice points per seeding brick (BTO_BRICK="bx,by,bz", product 64)
     int steps_since_rebin = 0;
     uint32_t* rebin_buf = nullptr;  // 4 x cap keys/values
     void* rebin_temp = nullptr;
@@ -129,6 +130,14 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     if (const char* e = std::getenv("BTO_BLOCKS_PER_CU")) c->blocks_per_cu_cap = std::atoi(e);
     if (const char* e = std::getenv("BTO_REBIN_EVERY")) c->rebin_every = std::atoi(e) > 0 ? std::atoi(e) : 0;
     if (const char* e = std::getenv("BTO_MORTON_SEED")) c->morton_seed = std::atoi(e) != 0;
+    if (const char* e = std::getenv("BTO_BRICK")) {
+        int b0 = 0, b1 = 0, b2 = 0;
+        if (std::sscanf(e, "%d,%d,%d", &b0, &b1, &b2) == 3 && b0 > 0 && b1 > 0 && b2 > 0 && b0 * b1 * b2 == 64) {
+            c->brick[0] = b0;
+            c->brick[1] = b1;
+            c->brick[2] = b2;
+        }
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount >= NSEG)
         c->cus_per_xcd = prop.multiProcessorCount / NSEG;
@@ -199,10 +208,9 @@ static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hip
 
 // Re-sort the live particles of every segment by brick (Morton) order.
 static int rebin(bto_ctx* c, hipStream_t s) {
-    int bits = 1;
-    for (int d = 0; d < 3; ++d)
-        while ((1 << bits) < (c->blk.n[d] + 7) / 8) ++bits;
-    const uint32_t nbins = 1u << (3 * bits);
+    uint32_t nb[3];
+    for (int d = 0; d < 3; ++d) nb[d] = (uint32_t)((c->blk.n[d] + REBIN_BIN[d] - 1) / REBIN_BIN[d]);
+    const uint32_t nbins = nb[0] * nb[1] * nb[2];
     if (!c->rebin_buf) {
         const size_t tb = rebin_temp_bytes((int64_t)NSEG * nbins);
         if (tb == 0) return fail(c, BTO_EHIP, "rebin: scan storage query failed");
@@ -230,6 +238,8 @@ static int rebin(bto_ctx* c, hipStream_t s) {
     a.hist = c->rebin_buf + 2 * (size_t)c->cap;
     a.offs = a.hist + (size_t)NSEG * nbins;
     a.nbins = nbins;
+    a.nbx = nb[0];
+    a.nby = nb[1];
     a.temp = c->rebin_temp;
     a.temp_bytes = c->rebin_temp_bytes;
     hipError_t e = launch_rebin(a, s);
@@ -258,6 +268,7 @@ int bto_seed(bto_ctx* c, int32_t stride, const double* offset3, int64_t* n_seeds
                                 (long long)c->cap);
     a.stride = stride;
     a.P = P;
+    for (int d = 0; d < 3; ++d) a.brick[d] = c->brick[d];
     {
         // Morton brick order needs a cube of 4 * 2^k lattice points per axis (<= 4 * 256)
         const int32_t mb = a.m[0] / 4;

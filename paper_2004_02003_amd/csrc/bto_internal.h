@@ -40,6 +40,7 @@ struct SeedLatticeArgs {
     double off[3];       // lattice offset (cells)
     int32_t stride;
     int32_t morton;      // bricks in Morton order (power-of-two cube of bricks)
+    int32_t brick[3];    // lattice points per brick and axis (product 64)
     int64_t P;
     Segs segs;
     double origin[3], spacing[3];
@@ -98,6 +99,9 @@ struct AdjointArgs {
     uint8_t* status_out;        // P (may be null): status of the recomputed forward
 };
 
+// Rebin bins: REBIN_BIN[0] x REBIN_BIN[1] x REBIN_BIN[2] cells, x fastest.
+constexpr int REBIN_BIN[3] = {32, 2, 2};
+
 struct RebinArgs {
     int64_t P;                 // slots covered by the segments
     Segs segs;
@@ -110,7 +114,8 @@ struct RebinArgs {
     uint32_t* rank;            // per slot: rank inside the bin
     uint32_t* hist;            // NSEG * nbins counts (all zero between rebins)
     uint32_t* offs;            // NSEG * nbins exclusive prefix sums
-    uint32_t nbins;            // bricks (Morton index range) per segment
+    uint32_t nbins;            // bins per segment
+    uint32_t nbx, nby;         // bins along x and y
     void* temp;
     size_t temp_bytes;
 };

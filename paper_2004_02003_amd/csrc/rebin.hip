@@ -3,9 +3,11 @@
 // Particles start brick-ordered, so the 64 lanes of a wavefront read nearby
 // cells and share cache lines; as the flow disperses them that locality
 // decays and every lane touches its own lines.  Between advection launches the
-// live particles of each XCD segment are re-ordered by the Morton index of the
-// 8x8x8-cell brick that holds them (one brick ~ one wavefront of particles at
-// stride 2), with a counting sort:
+// live particles of each XCD segment are re-ordered by the 32x2x2-cell bin
+// that holds them, bins in x-fastest order (a wavefront's particles then lie
+// along a few grid rows, so each of a cell's row loads covers long runs of
+// contiguous memory -- the same reason the lattice is seeded x-fastest), with
+// a counting sort:
 //   count   - per particle, atomically increment its (segment, brick) bin;
 //             the old value is the particle's rank inside the bin;
 //   scan    - exclusive prefix sum over all bins (segment-major);
@@ -19,14 +21,6 @@
 
 namespace bto {
 
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 8 bits -> every third bit
-    v &= 0xFFu;
-    v = (v | (v << 8)) & 0x0000F00Fu;
-    v = (v | (v << 4)) & 0x000C30C3u;
-    v = (v | (v << 2)) & 0x00249249u;
-    return v;
-}
-
 __device__ __forceinline__ int segment_of(const Segs& sg, int64_t i) {
     int seg = 0;
 #pragma unroll
@@ -39,8 +33,8 @@ __global__ __launch_bounds__(BLOCK) void rebin_count_kernel(const RebinArgs a) {
         const int seg = segment_of(a.segs, i);
         if (i - a.segs.base[seg] >= (int64_t)a.count[seg]) continue;  // slot beyond the segment's live count
         const uint32_t c = a.pos[i].cell;
-        const uint32_t key = spread3((c & 1023u) >> 3) | (spread3(((c >> 10) & 1023u) >> 3) << 1) |
-                             (spread3(((c >> 20) & 1023u) >> 3) << 2);
+        const uint32_t key = (c & 1023u) / REBIN_BIN[0] +
+                             a.nbx * (((c >> 10) & 1023u) / REBIN_BIN[1] + a.nby * (((c >> 20) & 1023u) / REBIN_BIN[2]));
         const uint32_t bin = (uint32_t)seg * a.nbins + key;
         a.bin[i] = bin;
         a.rank[i] = atomicAdd(&a.hist[bin], 1u);

@@ -8,15 +8,16 @@ namespace bto {
 // Seeding.
 // ---------------------------------------------------------------------------
 
-// Lattice points are stored brick-major: bricks of 4x4x4 lattice points (one
-// wavefront) in x-fastest brick order, x-fastest inside a brick, so that a
-// wavefront's particles share cache lines of the field.  Bricks on the high
-// faces may be partial; slot(id) is the closed-form prefix count.
-__device__ __forceinline__ int64_t brick_slot(const int32_t m[3], int a, int b, int c) {
-    const int bx = a >> 2, by = b >> 2, bz = c >> 2;
-    const int lx = a & 3, ly = b & 3, lz = c & 3;
-    const int cx = min(4, m[0] - 4 * bx), cy = min(4, m[1] - 4 * by), cz = min(4, m[2] - 4 * bz);
-    return (int64_t)m[0] * m[1] * 4 * bz + (int64_t)m[0] * 4 * by * cz + (int64_t)4 * bx * cy * cz +
+// Lattice points are stored brick-major: bricks of B0 x B1 x B2 = 64 lattice
+// points (one wavefront; default 16 x 2 x 2, x-elongated so that each of a
+// cell's four row loads covers a few long contiguous runs of the grid) in
+// x-fastest brick order, x-fastest inside a brick.  Bricks on the high faces
+// may be partial; slot(id) is the closed-form prefix count.
+__device__ __forceinline__ int64_t brick_slot(const int32_t m[3], const int32_t B[3], int a, int b, int c) {
+    const int bx = a / B[0], by = b / B[1], bz = c / B[2];
+    const int lx = a % B[0], ly = b % B[1], lz = c % B[2];
+    const int cx = min(B[0], m[0] - B[0] * bx), cy = min(B[1], m[1] - B[1] * by), cz = min(B[2], m[2] - B[2] * bz);
+    return (int64_t)m[0] * m[1] * B[2] * bz + (int64_t)m[0] * B[1] * by * cz + (int64_t)B[0] * bx * cy * cz +
            lx + cx * (ly + cy * lz);
 }
 
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(BLOCK) void seed_lattice_kernel(const SeedLatticeAr
                              a.off[2] + (double)a.stride * ic};
         const int64_t slot = a.morton ? (int64_t)(spread3b(ia >> 2) | (spread3b(ib >> 2) << 1) | (spread3b(ic >> 2) << 2)) *
                                                 64 + ((ia & 3) + 4 * ((ib & 3) + 4 * (ic & 3)))
-                                      : brick_slot(a.m, ia, ib, ic);
+                                      : brick_slot(a.m, a.brick, ia, ib, ic);
         a.pos[slot] = pack(x);
         a.id[slot] = (uint32_t)t;
 #pragma unroll
