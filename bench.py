@@ -69,6 +69,47 @@ def algorithmic_bytes(per_launch, dt: str, stride: int):
     return total
 
 
+# Per-cycle time of the paper's own metric (Section 4.2: mean time per
+# non-write cycle of advection + particle management) on the paper's per-rank
+# ABC shape: a 64^3 block of a 256^3 domain (64 ranks), one period in 1000
+# steps, interval 50, reductions 1:1 and 1:8.  Context only: the paper's
+# times (Table 2) are V100 times inside Ascent/VTK-h, a different machine
+# and framework.
+PAPER_TABLE2_MS = {(50, 1): 6.6, (50, 2): 3.3}
+
+
+def paper_context(log):
+    import math
+    import torch
+    from bto_inputs import fields
+    from paper_2004_02003_amd import Context, InSituDriver, grid_to_device
+
+    n, interval, n_int = 64, 50, 4
+    s = fields.abc_noise(n, interval * n_int + 1, 2 * math.pi / 1000, sigma=0.0, global_n=256,
+                         offset=(64, 64, 64))
+    dev = [grid_to_device(g, "f32") for g in s.grids("f32")]
+    out = {}
+    for stride in (1, 2):
+        term = []
+
+        def keep(idx, fm, t0, t1, _term=term):
+            _term.append(float((fm["flag"] != 0).float().mean()))
+
+        with Context((n, n, n), n ** 3) as ctx:
+            drv = InSituDriver(ctx, interval=interval, stride=stride, on_flowmap=keep)
+            for c in range(len(dev)):
+                drv.cycle(dev[c], float(s.times[c]))
+            torch.cuda.synchronize()
+            ms = drv.mean_cycle_ms()
+        key = f"abc_64_block_1to{stride ** 3}_interval{interval}"
+        out[key] = {"ms_per_cycle": round(ms, 4),
+                    "discarded_pct": round(100 * sum(term) / len(term), 2),
+                    "paper_v100_ms_per_cycle": PAPER_TABLE2_MS[(interval, stride)]}
+        out[key]["particles"] = ((n - 1 - (stride - 1) // 2) // stride + 1) ** 3
+        log(f"paper context {key}: {ms:.4f} ms per cycle")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +298,9 @@ def main(argv=None):
             del dv
             torch.cuda.empty_cache()
         result["storage_variants"] = variants
+
+    if not args.no_variants and wl.name == "abc_128":
+        result["paper_context"] = paper_context(log)
 
     if not args.no_cpu_baseline:
         ids = np.arange(0, P, 1 if not turb else 1024)
