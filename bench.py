@@ -48,9 +48,8 @@ def field_bytes_per_point(dt: str) -> int:
     return 12 if dt == "f32" else 6
 
 
-def launch_plan(n_steps: int, kmax: int = 32):
-    kmax = int(os.environ.get("BTO_STEPS_PER_LAUNCH", kmax))
-    rb = int(os.environ.get("BTO_REBIN_EVERY", "0"))
+def launch_plan(n_steps: int, kmax: int, rb: int):
+    """The library's balanced split of one advect call into launches."""
     if 0 < rb < kmax:
         kmax = rb
     nl = (n_steps + kmax - 1) // kmax
@@ -110,6 +109,16 @@ def paper_context(log):
     return out
 
 
+# Launch shape per workload (results do not depend on it).  The coherent ABC
+# block runs best as seeded; the turbulent blocks mix their particles, so a
+# periodic re-sort restores cache locality, and for FP32 grids two lanes per
+# particle halve the cache lines a row load touches.
+LAUNCH_SHAPE = {
+    "turb_256": dict(rebin_every=5, lanes_per_particle=2),
+    "turb_512": dict(rebin_every=10, lanes_per_particle=2),
+}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +130,10 @@ def main(argv=None):
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--steps-per-launch", type=int, default=None,
                     help="RK4 steps fused into one advection launch (1..128; sets BTO_STEPS_PER_LAUNCH)")
+    ap.add_argument("--rebin-every", type=int, default=None,
+                    help="re-sort live particles every this many steps (0 = never; default per workload)")
+    ap.add_argument("--lanes-per-particle", type=int, default=None, choices=(1, 2),
+                    help="FP32 grids: lanes per particle (default per workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args(argv)
@@ -165,11 +178,19 @@ def main(argv=None):
     dcode = {"f32": _lib.BTO_F32, "f16": _lib.BTO_F16, "bf16": _lib.BTO_BF16}[dt]
 
     ctx = Context(wl.n, wl.n_seeds)
+    tune = dict(LAUNCH_SHAPE.get(wl.name, {}))
+    if args.rebin_every is not None:
+        tune["rebin_every"] = args.rebin_every
+    if args.lanes_per_particle is not None:
+        tune["lanes_per_particle"] = args.lanes_per_particle
+    if tune:
+        ctx.set_tuning(**tune)
+    tuning = ctx.tuning()
     P = ctx.seed(wl.stride)
     out = ctx.flowmap()
 
     # per-launch live counts and particle-steps (untimed pass, one call per launch)
-    plan = launch_plan(N)
+    plan = launch_plan(N, tuning["steps_per_launch"], tuning["rebin_every"])
     per_launch = []
     q = 0
     ctx.seed(wl.stride)
@@ -233,7 +254,8 @@ def main(argv=None):
                  "synthetic (seeded divergence-free Fourier-mode turbulence; no dataset)"),
         "config": {"workload": wl.name, "n": list(wl.n), "cycles": wl.n_cycles, "dt": wl.dt,
                    "stride": wl.stride, "seeds": P, "interval_steps": N, "storage": dt,
-                   "particle_steps_per_interval": int(psteps_interval), "valid_at_end": int(n_valid)},
+                   "particle_steps_per_interval": int(psteps_interval), "valid_at_end": int(n_valid),
+                   "tuning": tuning},
         "advect_only": {"value": round(psteps_interval / (adv_ms * 1e-3), 1), "ms": round(adv_ms, 4)},
         "roofline": roof,
     }

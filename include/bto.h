@@ -129,21 +129,31 @@ int bto_flowmap_out(bto_ctx *ctx, double *d_seed_xyz, double *d_end_xyz, uint8_t
 /* Counters of the current interval.  Synchronizes `stream`. */
 int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
 
-/* Launch-shape tuning of the advection (none of it changes results):
- *   steps_per_launch  RK4 steps fused into one kernel launch, 1..128
- *                     (default 32; launches are balanced to equal lengths);
- *   rebin_every       re-sort the live particles by 8x8x8-cell brick every
- *                     this many steps (restores cache locality as the flow
- *                     mixes them; 0 = never, the default);
- *   blocks_per_cu     cap on resident advection workgroups per compute unit
- *                     (0 = as many as the register budget allows).
+/* Launch-shape tuning of the advection (none of it changes which events
+ * happen; end positions agree to FP32 rounding):
+ *   steps_per_launch    RK4 steps fused into one kernel launch, 1..128
+ *                       (default 32; launches are balanced to equal lengths);
+ *   rebin_every         re-sort the live particles by 32x2x2-cell bin, bins in
+ *                       x-fastest order, every this many steps (restores cache
+ *                       locality as the flow mixes them; 0 = never, the default);
+ *   blocks_per_cu       cap on resident advection workgroups per compute unit
+ *                       (0 = as many as the register budget allows);
+ *   lanes_per_particle  1 (default) or 2.  With 2 and FP32 storage, the two
+ *                       lanes of a pair each load and weight one x-corner of
+ *                       every cell row and add their partial sums; this halves
+ *                       the cache lines a wavefront touches per row load at the
+ *                       cost of doubled per-particle ALU work, which pays on
+ *                       incoherent (mixed) particle sets.  16-bit storage
+ *                       always uses 1.
  * Defaults come from the environment variables BTO_STEPS_PER_LAUNCH,
- * BTO_REBIN_EVERY and BTO_BLOCKS_PER_CU when the context is created.
- * BTO_EINVAL for values out of range; takes effect on the next advect call. */
+ * BTO_REBIN_EVERY, BTO_BLOCKS_PER_CU and BTO_LANES_PER_PARTICLE when the
+ * context is created.  BTO_EINVAL for values out of range; takes effect on
+ * the next advect call. */
 typedef struct {
     int32_t steps_per_launch;
     int32_t rebin_every;
     int32_t blocks_per_cu;
+    int32_t lanes_per_particle;
 } bto_tuning;
 
 int bto_set_tuning(bto_ctx *ctx, const bto_tuning *t);

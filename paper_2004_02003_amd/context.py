@@ -87,15 +87,19 @@ class Context:
         t = _lib.Tuning()
         self._check(self.L.bto_get_tuning(self._h, ctypes.byref(t)))
         return dict(steps_per_launch=t.steps_per_launch, rebin_every=t.rebin_every,
-                    blocks_per_cu=t.blocks_per_cu)
+                    blocks_per_cu=t.blocks_per_cu, lanes_per_particle=t.lanes_per_particle)
 
-    def set_tuning(self, steps_per_launch=None, rebin_every=None, blocks_per_cu=None):
-        """Launch shape of the advection (never changes results)."""
+    def set_tuning(self, steps_per_launch=None, rebin_every=None, blocks_per_cu=None,
+                   lanes_per_particle=None):
+        """Launch shape of the advection (events unchanged; positions agree
+        to FP32 rounding)."""
         cur = self.tuning()
         t = _lib.Tuning()
         t.steps_per_launch = cur["steps_per_launch"] if steps_per_launch is None else int(steps_per_launch)
         t.rebin_every = cur["rebin_every"] if rebin_every is None else int(rebin_every)
         t.blocks_per_cu = cur["blocks_per_cu"] if blocks_per_cu is None else int(blocks_per_cu)
+        t.lanes_per_particle = (cur["lanes_per_particle"] if lanes_per_particle is None
+                                else int(lanes_per_particle))
         self._check(self.L.bto_set_tuning(self._h, ctypes.byref(t)))
 
     # -- the path ----------------------------------------------------------

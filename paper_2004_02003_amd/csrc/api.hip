@@ -26,6 +26,7 @@ struct bto_ctx {
     int steps_per_launch = 32;    // fused steps per advect launch, <= KMAX (BTO_STEPS_PER_LAUNCH)
     int blocks_per_cu_cap = 0;    // cap on resident advect workgroups per CU (BTO_BLOCKS_PER_CU; 0 = occupancy)
     int rebin_every = 0;          // re-sort live particles every this many steps (BTO_REBIN_EVERY; 0 = never)
+    int lanes_per_particle = 1;   // FP32 grids: 1 or 2 lanes per particle (BTO_LANES_PER_PARTICLE)
     int morton_seed = 0;          // Morton brick order at seeding when possible (BTO_MORTON_SEED)
     int brick[3] = {64, 1, 1};    // lattice points per seeding brick (BTO_BRICK="bx,by,bz", product 64)
     int steps_since_rebin = 0;
@@ -130,6 +131,7 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     if (const char* e = std::getenv("BTO_BLOCKS_PER_CU")) c->blocks_per_cu_cap = std::atoi(e);
     if (const char* e = std::getenv("BTO_REBIN_EVERY")) c->rebin_every = std::atoi(e) > 0 ? std::atoi(e) : 0;
     if (const char* e = std::getenv("BTO_MORTON_SEED")) c->morton_seed = std::atoi(e) != 0;
+    if (const char* e = std::getenv("BTO_LANES_PER_PARTICLE")) c->lanes_per_particle = std::atoi(e) == 2 ? 2 : 1;
     if (const char* e = std::getenv("BTO_BRICK")) {
         int b0 = 0, b1 = 0, b2 = 0;
         if (std::sscanf(e, "%d,%d,%d", &b0, &b1, &b2) == 3 && b0 > 0 && b1 > 0 && b2 > 0 && b0 * b1 * b2 == 64) {
@@ -346,9 +348,10 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     }
     int64_t max_seg = 0;
     for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
-    int per_cu = advect_max_blocks_per_cu(dtype, flags);
+    const int lpp = dtype == BTO_F32 ? c->lanes_per_particle : 1;
+    int per_cu = advect_max_blocks_per_cu(dtype, flags, lpp);
     if (c->blocks_per_cu_cap > 0 && c->blocks_per_cu_cap < per_cu) per_cu = c->blocks_per_cu_cap;
-    const int R = blocks_per_seg(c, max_seg, per_cu);
+    const int R = blocks_per_seg(c, max_seg * lpp, per_cu);
     // launches of (nearly) equal length, at most steps_per_launch steps each
     int kmax = c->steps_per_launch;
     if (c->rebin_every > 0 && c->rebin_every < kmax) kmax = c->rebin_every;
@@ -376,7 +379,7 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
         a.rec_pos = c->rec_pos;
         a.rec_meta = c->rec_meta;
         a.psteps = c->psteps;
-        hipError_t e = launch_advect(a, dtype, flags, R, s);
+        hipError_t e = launch_advect(a, dtype, flags, lpp, R, s);
         if (e != hipSuccess) return hip_fail(c, e, "advect launch");
         c->cur = 1 - c->cur;
         c->slot = (c->slot + 1) % 3;
@@ -546,6 +549,9 @@ int bto_set_tuning(bto_ctx* c, const bto_tuning* t) {
         return fail(c, BTO_EINVAL, "steps_per_launch must be in 1..%d", KMAX);
     if (t->rebin_every < 0) return fail(c, BTO_EINVAL, "rebin_every must be >= 0");
     if (t->blocks_per_cu < 0) return fail(c, BTO_EINVAL, "blocks_per_cu must be >= 0");
+    if (t->lanes_per_particle != 1 && t->lanes_per_particle != 2)
+        return fail(c, BTO_EINVAL, "lanes_per_particle must be 1 or 2");
+    c->lanes_per_particle = t->lanes_per_particle;
     c->steps_per_launch = t->steps_per_launch;
     c->rebin_every = t->rebin_every;
     c->blocks_per_cu_cap = t->blocks_per_cu;
@@ -557,6 +563,7 @@ int bto_get_tuning(const bto_ctx* c, bto_tuning* t) {
     t->steps_per_launch = c->steps_per_launch;
     t->rebin_every = c->rebin_every;
     t->blocks_per_cu = c->blocks_per_cu_cap;
+    t->lanes_per_particle = c->lanes_per_particle;
     return BTO_OK;
 }
 

@@ -189,6 +189,84 @@ __device__ __forceinline__ void trilerp_mid(const CA& A, const CA& B, const floa
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two lanes per particle (FP32 grids).  The pair (lanes 2m, 2m+1) carries the
+// same particle; lane h = lane & 1 keeps and loads only the x-corner h of
+// each of the cell's four rows: 12 bytes, one dwordx3 load per row, and the
+// pair's loads are adjacent in memory, so a wavefront's row load covers one
+// contiguous run with half the cache-line accesses per particle of the
+// one-lane layout.  Each lane forms the partial trilinear sum over its
+// corners and adds its partner's with one DPP lane swap; both then hold the
+// same velocity (a + b == b + a), so positions and decisions stay identical.
+// ---------------------------------------------------------------------------
+struct __attribute__((packed, aligned(4))) Pt32 { float v[3]; };
+
+struct PairCache {
+    uint32_t base;
+    uint32_t h;      // x-corner of this lane (0 or 1)
+    float R[4][3];   // corner (h, row) of each row r
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
+        const Pt32 x = *reinterpret_cast<const Pt32*>(V + (uint64_t)(pt + h) * 12u);
+        R[r][0] = x.v[0];
+        R[r][1] = x.v[1];
+        R[r][2] = x.v[2];
+    }
+};
+
+template <int DT>
+__device__ __forceinline__ void ensure(const Geom& g, const char* V, uint32_t base, PairCache& c) {
+    if (c.base != base) {
+        c.load_row(V, base, 0);
+        c.load_row(V, base + g.sy, 1);
+        c.load_row(V, base + g.sz, 2);
+        c.load_row(V, base + g.sy + g.sz, 3);
+        c.base = base;
+    }
+}
+
+__device__ __forceinline__ float pair_sum(float v) {
+    // quad_perm(1, 0, 3, 2): the partner lane's value
+    const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false);
+    return v + __int_as_float(o);
+}
+
+__device__ __forceinline__ void pair_weights(const PairCache& A, const float f[3], float scale, float w[4]) {
+    const float wx = (A.h ? f[0] : 1.f - f[0]) * scale;
+    const float wz0 = (1.f - f[2]) * wx, wz1 = f[2] * wx;
+    w[0] = (1.f - f[1]) * wz0;
+    w[1] = f[1] * wz0;
+    w[2] = (1.f - f[1]) * wz1;
+    w[3] = f[1] * wz1;
+}
+
+__device__ __forceinline__ void trilerp(const PairCache& A, const float f[3], float out[3]) {
+    float w[4];
+    pair_weights(A, f, 1.f, w);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float acc = w[0] * A.R[0][c];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) acc = fmaf(w[r], A.R[r][c], acc);
+        out[c] = pair_sum(acc);
+    }
+}
+
+__device__ __forceinline__ void trilerp_mid(const PairCache& A, const PairCache& B, const float f[3], float out[3]) {
+    float w[4];
+    pair_weights(A, f, 0.5f, w);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float acc = w[0] * A.R[0][c];
+        acc = fmaf(w[0], B.R[0][c], acc);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            acc = fmaf(w[r], A.R[r][c], acc);
+            acc = fmaf(w[r], B.R[r][c], acc);
+        }
+        out[c] = pair_sum(acc);
+    }
+}
+
 // Trilinear value and its derivatives with respect to the in-cell offset
 // (d v_c / d f_d, which equals d v_c / d p_d in cell units); MID averages the
 // two levels per corner first (time midpoint).
@@ -241,9 +319,9 @@ __device__ __forceinline__ void stepper_init(Stepper<DT>& st) {
 // when frozen.  Each stage velocity is checked finite right after sampling;
 // each later stage point and the end point are checked inside the block, in
 // order.  On any event x is left at the step's start.
-template <int DT, int MODE>
+template <int DT, int MODE, class Cache>
 __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, double* x,
-                                        CellCache<DT>& LA, CellCache<DT>& LB) {
+                                        Cache& LA, Cache& LB) {
     const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
     float k1[3], k2[3], k3[3], k4[3];
     double y[3];

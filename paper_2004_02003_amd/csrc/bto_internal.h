@@ -124,9 +124,10 @@ hipError_t launch_seed_lattice(const SeedLatticeArgs& a, hipStream_t s);
 hipError_t launch_seed_explicit(const SeedExplicitArgs& a, hipStream_t s);
 hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, unsigned long long* psteps,
                              hipStream_t s);
-hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int blocks_per_seg, hipStream_t s);
+hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int lanes_per_particle, int blocks_per_seg,
+                         hipStream_t s);
 hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t s);
-int advect_max_blocks_per_cu(int dtype, int mode);
+int advect_max_blocks_per_cu(int dtype, int mode, int lanes_per_particle);
 hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s);
 size_t rebin_temp_bytes(int64_t nbins_total);

@@ -15,7 +15,7 @@ POS_TOL = 1e-5
 
 
 def run_gpu(n, grids_dev, times, stride=None, seeds=None, mode="linear", chunks=None, origin=(0, 0, 0),
-            spacing=(1, 1, 1), cap=None):
+            spacing=(1, 1, 1), cap=None, tuning=None):
     """Seed, advect (optionally in several calls), write the flow map; returns
     numpy arrays in seed order plus the counters."""
     import torch
@@ -27,6 +27,8 @@ def run_gpu(n, grids_dev, times, stride=None, seeds=None, mode="linear", chunks=
                                                                 for nd in n]))
     ctx = Context(n, max(int(cap), 1), origin=origin, spacing=spacing)
     try:
+        if tuning:
+            ctx.set_tuning(**tuning)
         if seeds is not None:
             ctx.seed_explicit(torch.as_tensor(np.ascontiguousarray(seeds, dtype=np.float64), device="cuda"))
         else:

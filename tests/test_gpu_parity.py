@@ -283,6 +283,35 @@ def test_rebin_between_launches_keeps_results():
         assert r["stats"]["particle_steps"] == a["stats"]["particle_steps"] or amb.any()
 
 
+def test_two_lanes_per_particle_matches_oracle_and_one_lane():
+    """Pairs of lanes per particle (each lane weights one x-corner of every
+    cell row, the pair adds its partial sums): same events as the oracle and
+    as one lane per particle, positions within FP32 rounding of both.  An odd
+    seed count leaves a half-filled last batch; rebinning and ragged calls
+    move particles between pairs and launches."""
+    n = (40, 36, 44)
+    N = 30
+    s = fields.abc_noise(n, N + 1, 0.05, sigma=0.05, seed=23, global_n=48)
+    gr = s.grids("f32")
+    dev = _dev(gr, "f32")
+    rng = np.random.default_rng(5)
+    seeds = rng.uniform(0.0, 1.0, size=(4001, 3)) * (np.array(n) - 1)
+    _say("two lanes per particle, 40x36x44, 4001 seeds")
+    a = run_gpu(n, dev, s.times, seeds=seeds)
+    b = run_gpu(n, dev, s.times, seeds=seeds, tuning=dict(lanes_per_particle=2))
+    c = run_gpu(n, dev, s.times, seeds=seeds, chunks=[3, 9, 1, 17],
+                tuning=dict(lanes_per_particle=2, rebin_every=4, steps_per_launch=7))
+    o = oracle.flowmap(oracle.Field(n, gr), s.times, seeds, N)
+    amb = o["margin"] < 1e-6
+    for r, lab in ((b, "2 lanes"), (c, "2 lanes, rebin, ragged calls")):
+        res = compare(r, o, label=lab)
+        assert 0.05 < res["terminated"] < 0.9
+        assert np.array_equal(r["flag"][~amb], a["flag"][~amb])
+        assert np.abs(r["end"] - a["end"]).max() < 5e-6
+        assert r["n_valid"] == int((r["flag"] == 0).sum())
+        assert r["stats"]["particle_steps"] == a["stats"]["particle_steps"] or amb.any()
+
+
 def test_error_paths_and_tuning_through_the_c_abi():
     """Validation happens before anything is enqueued: out-of-order calls,
     bad arguments and capacity overflow return the documented codes, the
@@ -319,8 +348,11 @@ def test_error_paths_and_tuning_through_the_c_abi():
         with pytest.raises(BTOError) as e:
             ctx.set_tuning(steps_per_launch=0)
         assert e.value.code == _lib.BTO_EINVAL
-        ctx.set_tuning(steps_per_launch=2, rebin_every=1, blocks_per_cu=1)
-        assert ctx.tuning() == dict(steps_per_launch=2, rebin_every=1, blocks_per_cu=1)
+        with pytest.raises(BTOError) as e:
+            ctx.set_tuning(lanes_per_particle=3)
+        assert e.value.code == _lib.BTO_EINVAL and "lanes_per_particle" in str(e.value)
+        ctx.set_tuning(steps_per_launch=2, rebin_every=1, blocks_per_cu=1, lanes_per_particle=2)
+        assert ctx.tuning() == dict(steps_per_launch=2, rebin_every=1, blocks_per_cu=1, lanes_per_particle=2)
         ctx.advect(dev, s.times)  # still usable after the failures
         fm = ctx.flowmap(count_valid=True)
         torch.cuda.synchronize()

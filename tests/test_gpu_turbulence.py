@@ -112,6 +112,8 @@ def test_turb_256_precision_workload_sampled_parity():
     for dt in wl.dtypes:
         _say(f"{wl.name} {dt} full size")
         with Context(wl.n, wl.n_seeds) as ctx:
+            # the launch shape the benchmark uses for this block (results must not change)
+            ctx.set_tuning(rebin_every=5, lanes_per_particle=2 if dt == "f32" else 1)
             ctx.seed(wl.stride)
             grids = _run_series(ctx, dev, s, wl.n_steps, dt)
             vmax = max(float(g.float().abs().max()) for g in grids[::10]) * 1.7320508
@@ -145,6 +147,7 @@ def test_turb_512_scale_workload_ring_and_jacobian_subset():
     ids = np.arange(0, wl.n_seeds, 4099)
     seeds_all = oracle.seed_lattice(wl.n, wl.stride)
     with Context(wl.n, wl.n_seeds) as ctx:
+        ctx.set_tuning(rebin_every=10)  # re-sort every 10 steps (results must not change)
         ctx.seed(wl.stride)
         _run_series(ctx, dev, s, wl.n_steps, dt, ring=True)
         fm = ctx.flowmap(count_valid=True)
