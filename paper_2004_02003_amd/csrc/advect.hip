@@ -46,13 +46,6 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
             const PState ps = a.in_pos[sbase + i];
             id = a.in_id[sbase + i];
             unpack(ps, x);
-            {
-                // both levels of the starting cell in one round trip (the second
-                // stage usually stays in this cell)
-                const Cell c0 = locate(a.g, x);
-                ensure<DT>(a.g, a.f[0], c0.base, A);
-                if (MODE == MODE_LINEAR) ensure<DT>(a.g, a.f[1], c0.base, B);
-            }
             // two steps per iteration: the slots swap roles, so nothing is copied
             for (s = 0; s < a.K; ++s) {
                 status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], x, A, B);
