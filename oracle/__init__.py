@@ -63,7 +63,7 @@ def lib():
             build()
         L = ctypes.CDLL(_LIB)
         vp = ctypes.c_void_p
-        L.orc_flowmap.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32]
+        L.orc_flowmap.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32]
         L.orc_flowmap.restype = ctypes.c_int
         L.orc_adjoint.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int32]
         L.orc_adjoint.restype = ctypes.c_int
@@ -154,16 +154,19 @@ def seed_lattice(n, stride: int, off=None) -> np.ndarray:
 def flowmap(field: Field, times, seeds: np.ndarray, n_steps: int, mode: int = LINEAR,
             first_cycle: int = 0, jac: bool = False, nthreads: int = 0):
     """Run the interval for every seed; returns a dict of numpy arrays:
-    end (P,3), flag (P,), exit (P,), margin (P,), sig (P,), [jac (P,3,3)]."""
+    end (P,3), flag (P,), exit (P,), margin (P,), sig (P,), face (P,3) and
+    face_cond (P,) (exit point on the box surface for particles terminated in
+    a step, NaN otherwise, and its error-growth factor), [jac (P,3,3)]."""
     seeds = np.ascontiguousarray(seeds, dtype=np.float64).reshape(-1, 3)
     P = seeds.shape[0]
     pr, tkeep = _problem(field, times, n_steps, mode, first_cycle)
     out = dict(end=np.empty((P, 3)), flag=np.empty(P, np.uint8), exit=np.empty(P, np.int32),
-               margin=np.empty(P), sig=np.empty(P, np.uint64))
+               margin=np.empty(P), sig=np.empty(P, np.uint64), face=np.empty((P, 3)), face_cond=np.empty(P))
     J = np.empty((P, 3, 3)) if jac else None
     rc = lib().orc_flowmap(ctypes.byref(pr), P, seeds.ctypes.data, out["end"].ctypes.data,
                            out["flag"].ctypes.data, out["exit"].ctypes.data, out["margin"].ctypes.data,
-                           out["sig"].ctypes.data, J.ctypes.data if jac else None, int(nthreads))
+                           out["sig"].ctypes.data, J.ctypes.data if jac else None, out["face"].ctypes.data,
+                           out["face_cond"].ctypes.data, int(nthreads))
     if rc != 0:
         raise ValueError("oracle rejected the problem (bad sizes or non-increasing times)")
     if jac:

@@ -29,7 +29,13 @@
  *  - a non-finite velocity sample (tested right after each stage sample)
  *    flags the particle INVALID at that step, position likewise frozen;
  *  - a seed outside the box is TERMINATED at exit step 0;
- *  - the sampling cell is i_d = min(floor(p_d), n_d - 2), f_d = p_d - i_d.
+ *  - the sampling cell is i_d = min(floor(p_d), n_d - 2), f_d = p_d - i_d;
+ *  - the location where a terminated trajectory leaves the block (stored on
+ *    the boundary, which the paper's conclusion names as future work) is
+ *    taken as the point where the straight segment from the last inside
+ *    position x_n to the first outside point (the stage or end point that
+ *    triggered the termination) meets the box surface; seeds outside the box
+ *    from the start have none.
  *
  * Grid values are handed in through a fetch callback (dense arrays of
  * f64/f32/f16/bf16 are decoded exactly by orc_dense_fetch).
@@ -264,7 +270,45 @@ typedef struct {
     uint64_t sig;      /* hash of every stage's sampling cell */
     double phi[9];     /* tangent dx/dx0                        */
     double *stages;    /* optional: 4 stage points per step (N x 4 x 3) */
+    double face[3];    /* exit point on the box surface (NaN unless terminated in a step) */
+    double face_cond;  /* |y - x|_inf / |y_a - x_a| of that segment (NaN likewise) */
 } orc_track;
+
+/* Where the segment from the inside point x to the outside point y first meets
+ * the box [0, n-1]^3: the smallest fraction tau over the violated faces (ties
+ * to the lowest axis), that axis set exactly to its face value.  cond is the
+ * factor by which errors in x and y can grow in the exit point. */
+static void exit_face(const int32_t n[3], const double x[3], const double y[3], double f[3], double *cond)
+{
+    double tau = INFINITY, fv = 0.0;
+    int axis = -1;
+    for (int d = 0; d < 3; ++d) {
+        const double hi = (double)(n[d] - 1);
+        double t = INFINITY, v = 0.0;
+        if (y[d] < 0.0) {
+            t = (0.0 - x[d]) / (y[d] - x[d]);
+            v = 0.0;
+        } else if (y[d] > hi) {
+            t = (hi - x[d]) / (y[d] - x[d]);
+            v = hi;
+        }
+        if (t < tau) {
+            tau = t;
+            axis = d;
+            fv = v;
+        }
+    }
+    double span = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        f[d] = x[d] + tau * (y[d] - x[d]);
+        const double hi = (double)(n[d] - 1);
+        if (f[d] < 0.0) f[d] = 0.0;
+        if (f[d] > hi) f[d] = hi;
+        if (fabs(y[d] - x[d]) > span) span = fabs(y[d] - x[d]);
+    }
+    f[axis] = fv;
+    *cond = span / fabs(y[axis] - x[axis]);
+}
 
 static const double STAGE_THETA[4] = {0.0, 0.5, 0.5, 1.0};
 
@@ -275,6 +319,8 @@ static void advect_one(const orc_problem *P, const double x0[3], int want_phi, o
     double phi[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     uint64_t sig = 0xcbf29ce484222325ull;
     double margin = face_distance(P->n, x);
+    T->face[0] = T->face[1] = T->face[2] = NAN;
+    T->face_cond = NAN;
     int flag = ORC_VALID;
     int32_t exit = N;
     if (!inside(P->n, x)) {
@@ -294,7 +340,11 @@ static void advect_one(const orc_problem *P, const double x0[3], int want_phi, o
                 for (int d = 0; d < 3; ++d) y[st][d] = x[d] + a[st] * k[st - 1][d];
                 const double fd = face_distance(P->n, y[st]);
                 if (fd < margin) margin = fd;
-                if (!inside(P->n, y[st])) { event = ORC_TERMINATED; break; }
+                if (!inside(P->n, y[st])) {
+                    event = ORC_TERMINATED;
+                    exit_face(P->n, x, y[st], T->face, &T->face_cond);
+                    break;
+                }
                 if (want_phi) {
                     double Gd[9];
                     matmul3(G[st - 1], dy[st - 1], Gd);
@@ -314,8 +364,10 @@ static void advect_one(const orc_problem *P, const double x0[3], int want_phi, o
                 xn[d] = x[d] + (h / 6.0) * (k[0][d] + 2.0 * k[1][d] + 2.0 * k[2][d] + k[3][d]);
             const double fd = face_distance(P->n, xn);
             if (fd < margin) margin = fd;
-            if (!inside(P->n, xn)) event = ORC_TERMINATED;
-            else {
+            if (!inside(P->n, xn)) {
+                event = ORC_TERMINATED;
+                exit_face(P->n, x, xn, T->face, &T->face_cond);
+            } else {
                 if (want_phi) {
                     double Gd[4][9];
                     for (int st = 0; st < 4; ++st) matmul3(G[st], dy[st], Gd[st]);
@@ -350,7 +402,8 @@ static void set_threads(int32_t nthreads)
 /* Flow map of P seeds: end position, flag, exit step; optional face margin,
  * stage-cell signature and tangent Phi (row-major dx_end/dx0). */
 int orc_flowmap(const orc_problem *P, int64_t np, const double *seeds, double *end, uint8_t *flag,
-                int32_t *exit_step, double *margin, uint64_t *cellsig, double *jac, int32_t nthreads)
+                int32_t *exit_step, double *margin, uint64_t *cellsig, double *jac, double *face,
+                double *face_cond, int32_t nthreads)
 {
     if (!P || !P->times || !P->fetch || P->n_steps < 0) return -1;
     for (int d = 0; d < 3; ++d)
@@ -369,6 +422,8 @@ int orc_flowmap(const orc_problem *P, int64_t np, const double *seeds, double *e
         if (margin) margin[p] = T.margin;
         if (cellsig) cellsig[p] = T.sig;
         if (jac) memcpy(jac + 9 * p, T.phi, 9 * sizeof(double));
+        if (face) memcpy(face + 3 * p, T.face, 3 * sizeof(double));
+        if (face_cond) face_cond[p] = T.face_cond;
     }
     return 0;
 }

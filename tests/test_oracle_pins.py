@@ -399,3 +399,153 @@ def test_nonfinite_velocity_flags_invalid():
     # step 1 is the first to read cycle 2 (its stages 2-4), in cell (4, 5, 5)
     assert r["exit"][0] == 1
     assert np.all(np.isfinite(r["end"][0]))
+
+
+# ---------------------------------------------------------------------------
+# Exit point on the block surface (a terminated particle's last segment, from
+# its last inside position to the first outside point, cut at the surface).
+# ---------------------------------------------------------------------------
+def test_exit_point_of_uniform_flow_is_the_line_face_crossing():
+    rng = np.random.default_rng(11)
+    n = (14, 12, 10)
+    N = 25
+    times = np.concatenate([[0.0], np.cumsum(rng.uniform(0.2, 0.6, N))])
+    hi = np.array(n, dtype=float) - 1
+    checked = 0
+    for u in (np.array([0.9, -0.35, 0.2]), np.array([-0.4, 0.6, -0.75])):
+        s = fields.uniform_flow(n, u, times)
+        F = oracle.Field(n, s.grids("f64"))
+        seeds = oracle.seed_lattice(n, 2)
+        r = oracle.flowmap(F, times, seeds, N)
+        for p, x0 in enumerate(seeds):
+            # time at which the straight line x0 + u t leaves the box, per face
+            t_face = np.where(u > 0, (hi - x0) / u, np.where(u < 0, -x0 / u, np.inf))
+            t_star = t_face.min()
+            if r["flag"][p] != oracle.TERMINATED:
+                assert np.all(np.isnan(r["face"][p]))
+                continue
+            a = int(np.argmin(t_face))
+            if np.sort(t_face)[1] - t_star < 1e-9:
+                continue  # leaves through an edge: either face is right
+            checked += 1
+            np.testing.assert_allclose(r["face"][p], x0 + u * t_star, atol=1e-11)
+            assert r["face"][p][a] == (hi[a] if u[a] > 0 else 0.0)
+            assert r["face_cond"][p] == pytest.approx(np.abs(u).max() / abs(u[a]), rel=1e-12)
+    assert checked > 300
+
+
+def _rk4_rotation_stages(z, c3, Omega, h, w):
+    """Classic RK4 stage points of dz/dt = i Omega z (complex, about the axis),
+    vertical speed w: the three stage points and the step end."""
+    k1 = 1j * Omega * z
+    z2 = z + h / 2 * k1
+    k2 = 1j * Omega * z2
+    z3 = z + h / 2 * k2
+    k3 = 1j * Omega * z3
+    z4 = z + h * k3
+    k4 = 1j * Omega * z4
+    zn = z + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return [(z2, c3 + h / 2 * w), (z3, c3 + h / 2 * w), (z4, c3 + h * w), (zn, c3 + h * w)]
+
+
+def test_exit_point_of_rotation_by_bisection_on_the_last_segment():
+    n = (16, 16, 6)
+    c = (5.5, 7.5)
+    radii = (5.0, 7.2)
+    Omega, w, h, N = 0.5, 0.0, 0.125, 60
+    times = np.arange(N + 1) * h
+    s = fields.solid_body_rotation(n, Omega, c, w, times)
+    F = oracle.Field(n, s.grids("f64"))
+    rng = np.random.default_rng(4)
+    r0 = rng.uniform(radii[0], radii[1], 200)
+    ph = rng.uniform(0, 2 * math.pi, 200)
+    seeds = np.stack([c[0] + r0 * np.cos(ph), c[1] + r0 * np.sin(ph), np.full(200, 1.5)], axis=1)
+    hi = np.array(n, dtype=float) - 1
+    seeds = seeds[np.all((seeds >= 0) & (seeds <= hi), axis=1)]  # start inside the box
+    res = oracle.flowmap(F, times, seeds, N)
+
+    def inside(p):
+        return bool(np.all(p >= 0) and np.all(p <= hi))
+
+    kinds = []
+    for p in range(len(seeds)):
+        z = (seeds[p, 0] - c[0]) + 1j * (seeds[p, 1] - c[1])
+        x = seeds[p].copy()
+        out = None
+        for st in range(N):
+            for kind, (zz, zc) in enumerate(_rk4_rotation_stages(z, x[2], Omega, h, w)):
+                q = np.array([c[0] + zz.real, c[1] + zz.imag, zc])
+                if not inside(q):
+                    out = q
+                    break
+            if out is not None:
+                break
+            zz, zc = _rk4_rotation_stages(z, x[2], Omega, h, w)[-1]
+            z = zz
+            x = np.array([c[0] + z.real, c[1] + z.imag, zc])
+        if out is None:
+            assert res["flag"][p] == oracle.VALID and np.all(np.isnan(res["face"][p]))
+            continue
+        if np.min(np.minimum(np.abs(out), np.abs(hi - out))) < 1e-9:
+            continue  # outside point on a face to rounding: the event is a tie
+        assert res["flag"][p] == oracle.TERMINATED and res["exit"][p] == st
+        np.testing.assert_allclose(res["end"][p], x, atol=1e-10)
+        lo_t, hi_t = 0.0, 1.0  # largest fraction of the segment still inside
+        for _ in range(80):
+            mid = 0.5 * (lo_t + hi_t)
+            lo_t, hi_t = (mid, hi_t) if inside(x + mid * (out - x)) else (lo_t, mid)
+        f = x + lo_t * (out - x)
+        np.testing.assert_allclose(res["face"][p], f, atol=1e-9)
+        # on the surface: one coordinate exactly on a face, all inside
+        assert inside(res["face"][p])
+        assert np.min(np.minimum(res["face"][p], hi - res["face"][p])) == 0.0
+        kinds.append(kind)
+    assert len(kinds) >= 15
+
+
+def test_exit_point_when_only_the_step_end_leaves():
+    """Two cycles, u_x = U everywhere; u_y = -a at cycle 0 and at cycle 1 for
+    x <= 9, +B for x >= 10 (a ramp across the cell in between).  Seeds with
+    x in [6, 7] and h U = 4 put the stage points y2, y3 at x + 2 (u_y = -a at
+    both stage times) and y4 at x + 4 (u_y = B at theta = 1), so k = (U, -a),
+    (U, -a), (U, -a), (U, B) exactly: every stage point moves down while the
+    step end moves up by h (B - 5a) / 6 and leaves through the top face."""
+    n = (16, 16, 4)
+    U, a, B, h = 2.0, 0.1, 2.0, 2.0
+    g0 = np.zeros((n[2], n[1], n[0], 3))
+    g0[..., 0] = U
+    g0[..., 1] = -a
+    g1 = g0.copy()
+    g1[:, :, 10:, 1] = B
+    F = oracle.Field(n, [g0, g1])
+    times = np.array([0.0, h])
+    rng = np.random.default_rng(9)
+    P = 200
+    seeds = np.stack([rng.uniform(6.0, 7.0, P), rng.uniform(13.0, 15.0, P), rng.uniform(0.5, 2.5, P)], axis=1)
+    r = oracle.flowmap(F, times, seeds, 1)
+    dy = h * (B - 5 * a) / 6
+    xn = seeds + np.array([h * U, dy, 0.0])
+    leaves = xn[:, 1] > 15.0
+    assert 30 < leaves.sum() < P - 30
+    assert np.all(r["flag"][leaves] == oracle.TERMINATED) and np.all(r["exit"][leaves] == 0)
+    np.testing.assert_allclose(r["end"][leaves], seeds[leaves], atol=0)
+    tau = (15.0 - seeds[leaves, 1]) / dy
+    np.testing.assert_allclose(r["face"][leaves], seeds[leaves] + tau[:, None] * (xn[leaves] - seeds[leaves]),
+                               atol=1e-12)
+    assert np.all(r["face"][leaves][:, 1] == 15.0)
+    np.testing.assert_allclose(r["face_cond"][leaves], h * U / dy, rtol=1e-12)
+    assert np.all(r["flag"][~leaves] == oracle.VALID) and np.all(np.isnan(r["face"][~leaves]))
+    np.testing.assert_allclose(r["end"][~leaves], xn[~leaves], atol=1e-12)
+
+
+def test_exit_point_absent_for_outside_seeds_and_invalid_particles():
+    n = (10, 10, 10)
+    s = fields.uniform_flow(n, [0.5, 0.0, 0.0], np.arange(6) * 0.2)
+    gs = s.grids("f64")
+    gs[2][5, 5, 5] = np.nan
+    F = oracle.Field(n, gs)
+    seeds = np.array([[4.0, 5.0, 5.0], [-0.5, 3.0, 3.0], [8.7, 2.0, 2.0]])
+    r = oracle.flowmap(F, s.times, seeds, 5)
+    assert r["flag"].tolist() == [oracle.INVALID, oracle.TERMINATED, oracle.TERMINATED]
+    assert np.all(np.isnan(r["face"][:2])) and np.isnan(r["face_cond"][:2]).all()
+    np.testing.assert_allclose(r["face"][2], [9.0, 2.0, 2.0], atol=1e-12)
