@@ -59,6 +59,12 @@ typedef enum { BTO_F32 = 0, BTO_F16 = 1, BTO_BF16 = 2 } bto_dtype;
  * the grid of cycle n (the single-time-step in situ constraint of Section 2.2). */
 enum { BTO_TIME_LINEAR = 0, BTO_TIME_FROZEN = 1 };
 
+/* Flag bit of bto_advect_interval, OR-ed with the time mode: record, for every
+ * particle that this call terminates, the point where its trajectory left the
+ * block (read back with bto_exit_points).  Off by default: it costs a few
+ * percent of advection throughput. */
+enum { BTO_RECORD_EXIT = 2 };
+
 /* Per-seed outcome in the flow map. */
 enum { BTO_VALID = 0, BTO_TERMINATED = 1, BTO_INVALID = 2 };
 
@@ -108,7 +114,7 @@ int bto_seed_explicit(bto_ctx *ctx, const double *d_xyz, int64_t n, void *stream
  * times; step s uses h = times[s+1] - times[s].  May be called repeatedly
  * within one interval (e.g. once per cycle with two grids): steps accumulate
  * and exit steps count from the seeding.  flags: BTO_TIME_LINEAR or
- * BTO_TIME_FROZEN.  Termination rule: the stage points y2, y3, y4 and the
+ * BTO_TIME_FROZEN, optionally | BTO_RECORD_EXIT.  Termination rule: the stage points y2, y3, y4 and the
  * step's end point are tested in that order; the first outside the block
  * terminates the particle in that step with its position frozen at the last
  * inside position; a non-finite velocity sample flags it INVALID likewise. */
@@ -125,6 +131,19 @@ int bto_advect_interval(bto_ctx *ctx, const void *const *d_fields, const double 
  * state is left unchanged (more steps may follow). */
 int bto_flowmap_out(bto_ctx *ctx, double *d_seed_xyz, double *d_end_xyz, uint8_t *d_flag,
                     int32_t *d_exit_step, int64_t *n_valid_out, void *stream);
+
+/* Exit points of the interval so far, in seed-id order: for every seed
+ * terminated during a step, the world coordinates of the point where its
+ * trajectory left the block (storing termination locations on the boundary
+ * is the future work named in the paper's conclusion).  The exit point is
+ * where the straight segment from the particle's last inside position to
+ * the first outside point (the RK4 stage or step end that terminated it)
+ * meets the block surface; one coordinate lies exactly on a face.
+ * d_exit_xyz: n x 3 doubles on the device, written on `stream` (async);
+ * NaN for valid and invalid seeds, for seeds outside the block at seeding
+ * and for particles terminated by a call made without BTO_RECORD_EXIT.
+ * BTO_ESTATE before seeding. */
+int bto_exit_points(bto_ctx *ctx, double *d_exit_xyz, void *stream);
 
 /* Counters of the current interval.  Synchronizes `stream`. */
 int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);

@@ -17,12 +17,13 @@ LIB_PATH = os.environ.get("BTO_LIB_PATH") or os.path.join(HERE, "libbto.so")
 BTO_OK, BTO_EINVAL, BTO_ENOMEM, BTO_EHIP, BTO_ESTATE, BTO_ERANGE = 0, -1, -2, -3, -4, -5
 BTO_F32, BTO_F16, BTO_BF16 = 0, 1, 2
 BTO_TIME_LINEAR, BTO_TIME_FROZEN = 0, 1
+BTO_RECORD_EXIT = 2
 BTO_VALID, BTO_TERMINATED, BTO_INVALID = 0, 1, 2
 
 EXPORTED = [
     "bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
     "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle",
-    "bto_set_tuning", "bto_get_tuning",
+    "bto_set_tuning", "bto_get_tuning", "bto_exit_points",
 ]
 
 _ERRNAMES = {BTO_EINVAL: "BTO_EINVAL", BTO_ENOMEM: "BTO_ENOMEM", BTO_EHIP: "BTO_EHIP",
@@ -72,6 +73,7 @@ def load() -> ctypes.CDLL:
     L.bto_seed_explicit.argtypes = [vp, vp, i64, vp]
     L.bto_advect_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp]
     L.bto_flowmap_out.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
+    L.bto_exit_points.argtypes = [vp, vp, vp]
     L.bto_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
     L.bto_adjoint_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
     L.bto_ftle.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]

@@ -20,6 +20,10 @@ _TORCH_DT = {torch.float32: _lib.BTO_F32, torch.float16: _lib.BTO_F16, torch.bfl
 _MODES = {"linear": _lib.BTO_TIME_LINEAR, "frozen": _lib.BTO_TIME_FROZEN}
 
 
+def _flags(mode: str, record_exit: bool) -> int:
+    return _MODES[mode] | (_lib.BTO_RECORD_EXIT if record_exit else 0)
+
+
 def _stream_ptr(stream) -> Optional[int]:
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -117,8 +121,11 @@ class Context:
         self.n_seeds = int(xyz.shape[0])
         return self.n_seeds
 
-    def advect(self, grids: Sequence[torch.Tensor], times, mode: str = "linear", stream=None):
-        """n = len(grids) - 1 RK4 steps through the given consecutive cycles."""
+    def advect(self, grids: Sequence[torch.Tensor], times, mode: str = "linear", record_exit: bool = False,
+               stream=None):
+        """n = len(grids) - 1 RK4 steps through the given consecutive cycles;
+        ``record_exit`` keeps the exit point of every particle terminated here
+        (``exit_points``)."""
         if len(grids) < 2:
             raise ValueError("need at least two grids (one step)")
         dt = grids[0].dtype
@@ -133,14 +140,14 @@ class Context:
             raise ValueError("one time per grid")
         ptrs = (ctypes.c_void_p * len(grids))(*[g.data_ptr() for g in grids])
         self._check(self.L.bto_advect_interval(self._h, ptrs, times.ctypes.data, len(grids) - 1,
-                                               _TORCH_DT[dt], _MODES[mode], _stream_ptr(stream)))
+                                               _TORCH_DT[dt], _flags(mode, record_exit), _stream_ptr(stream)))
 
-    def advect_ptrs(self, ptrs, times, dtype: int, mode: str = "linear", stream=None):
+    def advect_ptrs(self, ptrs, times, dtype: int, mode: str = "linear", record_exit: bool = False, stream=None):
         """Same as ``advect`` with raw device pointers (no per-call tensor checks)."""
         arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
         t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
         self._check(self.L.bto_advect_interval(self._h, arr, t.ctypes.data, len(ptrs) - 1, int(dtype),
-                                               _MODES[mode], _stream_ptr(stream)))
+                                               _flags(mode, record_exit), _stream_ptr(stream)))
 
     def flowmap(self, with_seeds: bool = True, count_valid: bool = False, out=None, stream=None):
         """Seed-ordered flow map: dict with end (P,3) f64, flag (P,) u8,
@@ -160,6 +167,16 @@ class Context:
             ctypes.byref(nv) if count_valid else None, _stream_ptr(stream)))
         if count_valid:
             out["n_valid"] = int(nv.value)
+        return out
+
+    def exit_points(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """(P, 3) float64: where each terminated trajectory left the block
+        (world coordinates, on the block surface); NaN for other seeds."""
+        if out is None:
+            out = torch.empty((self.n_seeds, 3), dtype=torch.float64, device=torch.device("cuda", self.device))
+        if out.dtype != torch.float64 or tuple(out.shape) != (self.n_seeds, 3) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous (P, 3) float64 device tensor")
+        self._check(self.L.bto_exit_points(self._h, out.data_ptr(), _stream_ptr(stream)))
         return out
 
     def adjoint(self, grids: Sequence[torch.Tensor], times, cot: torch.Tensor, grad_grids=None,

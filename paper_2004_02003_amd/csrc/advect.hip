@@ -10,7 +10,7 @@ namespace bto {
 template <int DT, int LPP> struct CacheOf { using T = CellCache<DT>; };
 template <> struct CacheOf<DT_F32, 2> { using T = PairCache; };
 
-template <int DT, int MODE, int LPP>
+template <int DT, int MODE, int LPP, int REC>
 __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
     using Cache = typename CacheOf<DT, LPP>::T;
     constexpr int W = BLOCK / WAVE;
@@ -46,14 +46,19 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
             const PState ps = a.in_pos[sbase + i];
             id = a.in_id[sbase + i];
             unpack(ps, x);
+            // a terminated particle's outside point, kept as its offset from x
+            const auto on_exit = [&](const double* y) {
+                if constexpr (REC)
+                    a.rec_out[id] = make_float4((float)(y[0] - x[0]), (float)(y[1] - x[1]), (float)(y[2] - x[2]), 0.f);
+            };
             // two steps per iteration: the slots swap roles, so nothing is copied
             for (s = 0; s < a.K; ++s) {
-                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], x, A, B);
+                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], x, A, B, on_exit);
                 if (status != S_VALID) break;
                 A.base = NO_CELL;
                 if (MODE != MODE_LINEAR) B.base = NO_CELL;
                 if (++s >= a.K) break;
-                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], x, B, A);
+                status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], x, B, A, on_exit);
                 if (status != S_VALID) break;
                 B.base = NO_CELL;
                 if (MODE != MODE_LINEAR) A.base = NO_CELL;
@@ -84,7 +89,7 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
         }
         if (alive && !keep && owner) {
             a.rec_pos[id] = pack(x);
-            a.rec_meta[id] = (status << META_SHIFT) | (a.step0 + s);
+            a.rec_meta[id] = (status << META_SHIFT) | (a.step0 + s) | (REC && status == S_TERMINATED ? META_EXITPT : 0);
         }
         __syncthreads();  // s_cnt / s_base are reused by the next batch
     }
@@ -104,53 +109,45 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-template <int DT, int MODE, int LPP>
-static hipError_t launch_advect_t(const AdvectArgs& a, int R, hipStream_t s) {
-    hipLaunchKernelGGL((advect_kernel<DT, MODE, LPP>), dim3(R * NSEG), dim3(BLOCK), 0, s, a);
-    return hipGetLastError();
+// Every compiled variant: storage type, time mode, lanes per particle (two
+// only for FP32), exit-point recording.
+template <int DT_, int MODE_, int LPP_, int REC_>
+struct Variant {
+    static constexpr int DT = DT_, MODE = MODE_, LPP = LPP_, REC = REC_;
+};
+
+template <int DT, int LPP, class F>
+static auto with_mode_rec(int mode, int rec, F&& f) {
+    if (mode == MODE_LINEAR) return rec ? f(Variant<DT, MODE_LINEAR, LPP, 1>{}) : f(Variant<DT, MODE_LINEAR, LPP, 0>{});
+    return rec ? f(Variant<DT, MODE_FROZEN, LPP, 1>{}) : f(Variant<DT, MODE_FROZEN, LPP, 0>{});
 }
 
-template <int DT>
-static hipError_t launch_advect_m(const AdvectArgs& a, int mode, int lpp, int R, hipStream_t s) {
-    if constexpr (DT == DT_F32) {
-        if (lpp == 2)
-            return mode == MODE_LINEAR ? launch_advect_t<DT, MODE_LINEAR, 2>(a, R, s)
-                                       : launch_advect_t<DT, MODE_FROZEN, 2>(a, R, s);
-    }
-    return mode == MODE_LINEAR ? launch_advect_t<DT, MODE_LINEAR, 1>(a, R, s)
-                               : launch_advect_t<DT, MODE_FROZEN, 1>(a, R, s);
-}
-
-hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int lpp, int R, hipStream_t s) {
+template <class F>
+static auto with_variant(int dtype, int mode, int lpp, int rec, F&& f) {
     switch (dtype) {
-    case DT_F32: return launch_advect_m<DT_F32>(a, mode, lpp, R, s);
-    case DT_F16: return launch_advect_m<DT_F16>(a, mode, 1, R, s);
-    default: return launch_advect_m<DT_BF16>(a, mode, 1, R, s);
+    case DT_F32: return lpp == 2 ? with_mode_rec<DT_F32, 2>(mode, rec, f) : with_mode_rec<DT_F32, 1>(mode, rec, f);
+    case DT_F16: return with_mode_rec<DT_F16, 1>(mode, rec, f);
+    default: return with_mode_rec<DT_BF16, 1>(mode, rec, f);
     }
 }
 
-template <int DT, int MODE, int LPP>
-static int occ_t() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, advect_kernel<DT, MODE, LPP>, BLOCK, 0) != hipSuccess)
-        return 1;
-    return nb > 0 ? nb : 1;
+hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int lpp, int rec, int R, hipStream_t s) {
+    return with_variant(dtype, mode, lpp, rec, [&](auto v) {
+        using V = decltype(v);
+        hipLaunchKernelGGL((advect_kernel<V::DT, V::MODE, V::LPP, V::REC>), dim3(R * NSEG), dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    });
 }
 
-template <int DT>
-static int occ_m(int mode, int lpp) {
-    if constexpr (DT == DT_F32) {
-        if (lpp == 2) return mode == MODE_LINEAR ? occ_t<DT, MODE_LINEAR, 2>() : occ_t<DT, MODE_FROZEN, 2>();
-    }
-    return mode == MODE_LINEAR ? occ_t<DT, MODE_LINEAR, 1>() : occ_t<DT, MODE_FROZEN, 1>();
-}
-
-int advect_max_blocks_per_cu(int dtype, int mode, int lpp) {
-    switch (dtype) {
-    case DT_F32: return occ_m<DT_F32>(mode, lpp);
-    case DT_F16: return occ_m<DT_F16>(mode, 1);
-    default: return occ_m<DT_BF16>(mode, 1);
-    }
+int advect_max_blocks_per_cu(int dtype, int mode, int lpp, int rec) {
+    return with_variant(dtype, mode, lpp, rec, [](auto v) {
+        using V = decltype(v);
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, advect_kernel<V::DT, V::MODE, V::LPP, V::REC>, BLOCK,
+                                                         0) != hipSuccess)
+            return 1;
+        return nb > 0 ? nb : 1;
+    });
 }
 
 }  // namespace bto

@@ -40,6 +40,7 @@ struct bto_ctx {
     // per-seed records
     PState* rec_pos = nullptr;
     int32_t* rec_meta = nullptr;
+    float4* rec_out = nullptr;        // terminated particles: outside point - last inside position
     double* seed_xyz = nullptr;
     // counters: ring of 3 x NSEG live counts, then NSEG particle-step counters
     uint32_t* counts = nullptr;
@@ -151,6 +152,7 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     }
     ok = ok && hipMalloc(&c->rec_pos, P * sizeof(PState)) == hipSuccess;
     ok = ok && hipMalloc(&c->rec_meta, P * sizeof(int32_t)) == hipSuccess;
+    ok = ok && hipMalloc(&c->rec_out, P * sizeof(float4)) == hipSuccess;
     ok = ok && hipMalloc(&c->seed_xyz, P * 3 * sizeof(double)) == hipSuccess;
     ok = ok && hipMalloc(&c->counts, 3 * NSEG * sizeof(uint32_t) + 32 + NSEG * sizeof(unsigned long long)) == hipSuccess;
     if (!ok) {
@@ -174,6 +176,7 @@ int bto_destroy(bto_ctx* c) {
     }
     if (c->rec_pos) (void)hipFree(c->rec_pos);
     if (c->rec_meta) (void)hipFree(c->rec_meta);
+    if (c->rec_out) (void)hipFree(c->rec_out);
     if (c->seed_xyz) (void)hipFree(c->seed_xyz);
     if (c->counts) (void)hipFree(c->counts);
     if (c->adj_scratch) (void)hipFree(c->adj_scratch);
@@ -333,14 +336,17 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     if (!d_fields || !times) return fail(c, BTO_EINVAL, "null field or time array");
     if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
     if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
-    if (flags != BTO_TIME_LINEAR && flags != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    if ((flags & ~BTO_RECORD_EXIT) != BTO_TIME_LINEAR && (flags & ~BTO_RECORD_EXIT) != BTO_TIME_FROZEN)
+        return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    const int mode = flags & ~BTO_RECORD_EXIT;
+    const int rec = (flags & BTO_RECORD_EXIT) ? 1 : 0;
     for (int32_t q = 0; q <= n_steps; ++q)
         if (!d_fields[q]) return fail(c, BTO_EINVAL, "field pointer %d is null", q);
     for (int32_t q = 0; q < n_steps; ++q)
         if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
             return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
     if (!c->seeded) return fail(c, BTO_ESTATE, "advect called before seeding");
-    if ((int64_t)c->steps_done + n_steps >= (1 << 27)) return fail(c, BTO_ERANGE, "interval too long");
+    if ((int64_t)c->steps_done + n_steps > META_STEP) return fail(c, BTO_ERANGE, "interval too long");
     hipStream_t s = (hipStream_t)stream;
     if (c->n_seeds == 0) {
         c->steps_done += n_steps;
@@ -349,7 +355,7 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     int64_t max_seg = 0;
     for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
     const int lpp = dtype == BTO_F32 ? c->lanes_per_particle : 1;
-    int per_cu = advect_max_blocks_per_cu(dtype, flags, lpp);
+    int per_cu = advect_max_blocks_per_cu(dtype, mode, lpp, rec);
     if (c->blocks_per_cu_cap > 0 && c->blocks_per_cu_cap < per_cu) per_cu = c->blocks_per_cu_cap;
     const int R = blocks_per_seg(c, max_seg * lpp, per_cu);
     // launches of (nearly) equal length, at most steps_per_launch steps each
@@ -378,8 +384,9 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
         a.clear_count = c->counts + NSEG * ((c->slot + 2) % 3);
         a.rec_pos = c->rec_pos;
         a.rec_meta = c->rec_meta;
+        a.rec_out = c->rec_out;
         a.psteps = c->psteps;
-        hipError_t e = launch_advect(a, dtype, flags, lpp, R, s);
+        hipError_t e = launch_advect(a, dtype, mode, lpp, rec, R, s);
         if (e != hipSuccess) return hip_fail(c, e, "advect launch");
         c->cur = 1 - c->cur;
         c->slot = (c->slot + 1) % 3;
@@ -426,6 +433,29 @@ int bto_flowmap_out(bto_ctx* c, double* d_seed_xyz, double* d_end_xyz, uint8_t* 
         rc = bto_stats(c, &st, stream);
         if (rc) return rc;
         *n_valid_out = st.n_live;
+    }
+    return BTO_OK;
+}
+
+int bto_exit_points(bto_ctx* c, double* d_exit_xyz, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (!d_exit_xyz) return fail(c, BTO_EINVAL, "null output pointer");
+    if (!c->seeded) return fail(c, BTO_ESTATE, "exit_points called before seeding");
+    if (c->n_seeds > 0) {
+        FlowmapArgs a{};
+        a.P = c->n_seeds;
+        a.rec_pos = c->rec_pos;
+        a.rec_meta = c->rec_meta;
+        a.rec_out = c->rec_out;
+        a.g = c->geom;
+        for (int d = 0; d < 3; ++d) {
+            a.origin[d] = c->blk.origin[d];
+            a.spacing[d] = c->blk.spacing[d];
+        }
+        a.out_face = d_exit_xyz;
+        hipError_t e = launch_exit_points(a, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(c, e, "exit points launch");
     }
     return BTO_OK;
 }

@@ -27,8 +27,12 @@ constexpr int BLOCK = 256;
 enum : int { S_VALID = 0, S_TERMINATED = 1, S_INVALID = 2 };
 enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 enum : int { MODE_LINEAR = 0, MODE_FROZEN = 1 };
-constexpr int32_t META_LIVE = -1;  // record slot of a particle still advancing
-constexpr int META_SHIFT = 28;     // meta = flag << 28 | exit step
+// Per-seed record of an ended particle: flag << 28 | bits below | exit step.
+constexpr int32_t META_LIVE = -1;          // record slot of a particle still advancing
+constexpr int META_SHIFT = 28;
+constexpr int32_t META_OUTSIDE = 1 << 27;  // seeded outside the block
+constexpr int32_t META_EXITPT = 1 << 26;   // exit point recorded (terminated in a step)
+constexpr int32_t META_STEP = (1 << 26) - 1;
 
 struct __align__(16) PState {
     uint32_t cell;  // cx | cy << 10 | cz << 20
@@ -319,9 +323,42 @@ __device__ __forceinline__ void stepper_init(Stepper<DT>& st) {
 // when frozen.  Each stage velocity is checked finite right after sampling;
 // each later stage point and the end point are checked inside the block, in
 // order.  On any event x is left at the step's start.
-template <int DT, int MODE, class Cache>
+// Where the segment from the inside point x to the outside point y first meets
+// the box surface: the smallest fraction over the faces y violates (ties to
+// the lowest axis), that axis set exactly to its face value, the others
+// clamped into the box against rounding.  The exit location of a terminated
+// trajectory (its last inside position and the stage or end point that
+// terminated it).
+__device__ __forceinline__ void exit_face(const Geom& g, const double x[3], const double y[3], double f[3]) {
+    double tau = INFINITY, fv = 0.0;
+    int axis = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double t = INFINITY, v = 0.0;
+        if (y[d] < 0.0) {
+            t = (0.0 - x[d]) / (y[d] - x[d]);
+        } else if (y[d] > g.nmax[d]) {
+            t = (g.nmax[d] - x[d]) / (y[d] - x[d]);
+            v = g.nmax[d];
+        }
+        if (t < tau) {
+            tau = t;
+            axis = d;
+            fv = v;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double q = fma(tau, y[d] - x[d], x[d]);
+        f[d] = d == axis ? fv : fmin(fmax(q, 0.0), g.nmax[d]);
+    }
+}
+
+// One RK4 step.  On termination x keeps the last inside position and
+// `on_exit(y)` is called with the outside point that ended the particle.
+template <int DT, int MODE, class Cache, class OnExit>
 __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, double* x,
-                                        Cache& LA, Cache& LB) {
+                                        Cache& LA, Cache& LB, OnExit&& on_exit) {
     const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
     float k1[3], k2[3], k3[3], k4[3];
     double y[3];
@@ -333,7 +370,10 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     if (!finite3(k1)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = fma(0.5 * hs[d], (double)k1[d], x[d]);
-    if (!inside(g, y)) return S_TERMINATED;
+    if (!inside(g, y)) {
+        on_exit(y);
+        return S_TERMINATED;
+    }
 
     c = locate(g, y);
     ensure<DT>(g, V0, c.base, LA);
@@ -346,7 +386,10 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     if (!finite3(k2)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = fma(0.5 * hs[d], (double)k2[d], x[d]);
-    if (!inside(g, y)) return S_TERMINATED;
+    if (!inside(g, y)) {
+        on_exit(y);
+        return S_TERMINATED;
+    }
 
     c = locate(g, y);
     ensure<DT>(g, V0, c.base, LA);
@@ -359,7 +402,10 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     if (!finite3(k3)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) y[d] = fma(hs[d], (double)k3[d], x[d]);
-    if (!inside(g, y)) return S_TERMINATED;
+    if (!inside(g, y)) {
+        on_exit(y);
+        return S_TERMINATED;
+    }
 
     c = locate(g, y);
     if (MODE == MODE_LINEAR) {
@@ -375,7 +421,10 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
         const float ks = (k1[d] + k4[d]) + 2.0f * (k2[d] + k3[d]);
         y[d] = fma(hs[d] * (1.0 / 6.0), (double)ks, x[d]);
     }
-    if (!inside(g, y)) return S_TERMINATED;
+    if (!inside(g, y)) {
+        on_exit(y);
+        return S_TERMINATED;
+    }
     x[0] = y[0];
     x[1] = y[1];
     x[2] = y[2];
@@ -389,11 +438,12 @@ template <int DT, int MODE>
 __device__ __forceinline__ int rk4_step_alt(const Geom& g, const char* V0, const char* V1, double h, int s,
                                             Stepper<DT>& st) {
     int status;
+    const auto no_exit = [](const double*) {};
     if ((s & 1) == 0) {
-        status = rk4_step<DT, MODE>(g, V0, V1, h, st.x, st.A, st.B);
+        status = rk4_step<DT, MODE>(g, V0, V1, h, st.x, st.A, st.B, no_exit);
         if (MODE == MODE_LINEAR) st.A.base = NO_CELL;  // will receive level n+2
     } else {
-        status = rk4_step<DT, MODE>(g, V0, V1, h, st.x, st.B, st.A);
+        status = rk4_step<DT, MODE>(g, V0, V1, h, st.x, st.B, st.A, no_exit);
         if (MODE == MODE_LINEAR) st.B.base = NO_CELL;
     }
     if (MODE != MODE_LINEAR) st.A.base = st.B.base = NO_CELL;

@@ -32,6 +32,7 @@ struct AdvectArgs {
     uint32_t* clear_count;      // NSEG counts cleared for the launch after next
     PState* rec_pos;            // per seed id: final state of ended particles
     int32_t* rec_meta;          // per seed id: flag << 28 | exit step
+    float4* rec_out;            // per seed id: outside point - last inside position (terminated only)
     unsigned long long* psteps; // NSEG counters of attempted particle-steps
 };
 
@@ -73,12 +74,15 @@ struct FlowmapArgs {
     const uint32_t* id;
     const PState* rec_pos;
     const int32_t* rec_meta;
+    const float4* rec_out;
+    Geom g;
     const double* seed_xyz;
     double origin[3], spacing[3];
     double* out_seed;    // may be null
     double* out_end;
     uint8_t* out_flag;
     int32_t* out_exit;
+    double* out_face;    // exit points (bto_exit_points)
 };
 
 struct AdjointArgs {
@@ -124,10 +128,11 @@ hipError_t launch_seed_lattice(const SeedLatticeArgs& a, hipStream_t s);
 hipError_t launch_seed_explicit(const SeedExplicitArgs& a, hipStream_t s);
 hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, unsigned long long* psteps,
                              hipStream_t s);
-hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int lanes_per_particle, int blocks_per_seg,
-                         hipStream_t s);
+hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int lanes_per_particle, int record_exit,
+                         int blocks_per_seg, hipStream_t s);
+hipError_t launch_exit_points(const FlowmapArgs& a, hipStream_t s);
 hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t s);
-int advect_max_blocks_per_cu(int dtype, int mode, int lanes_per_particle);
+int advect_max_blocks_per_cu(int dtype, int mode, int lanes_per_particle, int record_exit);
 hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s);
 size_t rebin_temp_bytes(int64_t nbins_total);

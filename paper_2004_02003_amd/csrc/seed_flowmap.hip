@@ -71,7 +71,7 @@ __global__ __launch_bounds__(BLOCK) void seed_explicit_kernel(const SeedExplicit
             s.cell = 0;
             s.f[0] = s.f[1] = s.f[2] = 0.f;
             a.rec_pos[t] = s;  // position taken from seed_xyz by the writer
-            a.rec_meta[t] = (S_TERMINATED << META_SHIFT) | 0 | (1 << 27);
+            a.rec_meta[t] = (S_TERMINATED << META_SHIFT) | META_OUTSIDE;
         }
     }
 }
@@ -105,14 +105,14 @@ __global__ __launch_bounds__(BLOCK) void flowmap_records_kernel(const FlowmapArg
         }
         const int32_t meta = a.rec_meta[t];
         if (meta == META_LIVE) continue;
-        if (meta & (1 << 27)) {  // seeded outside the block
+        if (meta & META_OUTSIDE) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) a.out_end[3 * t + d] = a.seed_xyz[3 * t + d];
         } else {
             write_world(a, t, a.rec_pos[t]);
         }
         a.out_flag[t] = (uint8_t)(meta >> META_SHIFT);
-        a.out_exit[t] = meta & ((1 << 27) - 1);
+        a.out_exit[t] = meta & META_STEP;
     }
 }
 
@@ -128,6 +128,26 @@ __global__ __launch_bounds__(BLOCK) void flowmap_live_kernel(const FlowmapArgs a
         write_world(a, id, a.pos[sbase + i]);
         a.out_flag[id] = (uint8_t)S_VALID;
         a.out_exit[id] = a.steps_done;
+    }
+}
+
+// Exit points: world coordinates of the point where a terminated trajectory
+// left the block (when the advection recorded it); NaN for every other seed.
+__global__ __launch_bounds__(BLOCK) void exit_points_kernel(const FlowmapArgs a) {
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < a.P; t += (int64_t)gridDim.x * BLOCK) {
+        const int32_t meta = a.rec_meta[t];
+        double w[3] = {__builtin_nan(""), __builtin_nan(""), __builtin_nan("")};
+        if (meta != META_LIVE && (meta & META_EXITPT)) {
+            double x[3], f[3];
+            unpack(a.rec_pos[t], x);
+            const float4 o = a.rec_out[t];
+            const double y[3] = {x[0] + (double)o.x, x[1] + (double)o.y, x[2] + (double)o.z};
+            exit_face(a.g, x, y, f);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) w[d] = a.origin[d] + a.spacing[d] * f[d];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.out_face[3 * t + d] = w[d];
     }
 }
 
@@ -156,6 +176,13 @@ hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, un
     CountValues v;
     for (int q = 0; q < 3 * NSEG; ++q) v.v[q] = q < n ? values[q] : 0u;
     hipLaunchKernelGGL(set_counts_kernel, dim3(1), dim3(64), 0, s, counts, v, n, psteps);
+    return hipGetLastError();
+}
+
+hipError_t launch_exit_points(const FlowmapArgs& a, hipStream_t s) {
+    const int64_t nb = (a.P + BLOCK - 1) / BLOCK;
+    const int grid = (int)(nb < 4096 ? (nb > 0 ? nb : 1) : 4096);
+    hipLaunchKernelGGL(exit_points_kernel, dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

@@ -15,9 +15,10 @@ POS_TOL = 1e-5
 
 
 def run_gpu(n, grids_dev, times, stride=None, seeds=None, mode="linear", chunks=None, origin=(0, 0, 0),
-            spacing=(1, 1, 1), cap=None, tuning=None):
-    """Seed, advect (optionally in several calls), write the flow map; returns
-    numpy arrays in seed order plus the counters."""
+            spacing=(1, 1, 1), cap=None, tuning=None, record_exit=False):
+    """Seed, advect (optionally in several calls), write the flow map (and
+    with ``record_exit`` the exit points); returns numpy arrays in seed order
+    plus the counters."""
     import torch
     from paper_2004_02003_amd import Context
 
@@ -37,10 +38,12 @@ def run_gpu(n, grids_dev, times, stride=None, seeds=None, mode="linear", chunks=
             chunks = [N]
         q = 0
         for k in chunks:
-            ctx.advect(grids_dev[q:q + k + 1], times[q:q + k + 1], mode=mode)
+            ctx.advect(grids_dev[q:q + k + 1], times[q:q + k + 1], mode=mode, record_exit=record_exit)
             q += k
         assert q == N
         fm = ctx.flowmap(count_valid=True)
+        if record_exit:
+            fm["face"] = ctx.exit_points()
         st = ctx.stats()
         torch.cuda.synchronize()
         out = {k: v.cpu().numpy() for k, v in fm.items() if k != "n_valid"}
@@ -64,9 +67,25 @@ def compare(g, o, pos_tol=POS_TOL, margin=MARGIN, per_particle_tol=None, label="
     bad = np.nonzero(ok & (err > tol))[0]
     assert bad.size == 0, (f"{label}: end position error {err[bad[:5]]} > tol at {bad[:5]}; "
                            f"max err {err[ok].max():.3e}")
-    return dict(n=len(err), ambiguous=int(amb.sum()), max_err=float(err[ok].max()) if ok.any() else 0.0,
-                mean_err=float(err[ok].mean()) if ok.any() else 0.0,
-                terminated=float((o["flag"] == oracle.TERMINATED).mean()))
+    res = dict(n=len(err), ambiguous=int(amb.sum()), max_err=float(err[ok].max()) if ok.any() else 0.0,
+               mean_err=float(err[ok].mean()) if ok.any() else 0.0,
+               terminated=float((o["flag"] == oracle.TERMINATED).mean()))
+    if "face" in g and "face" in o:
+        # exit points: present exactly where the oracle has one; errors in the
+        # last inside and first outside points grow by the segment's factor
+        has = ~np.isnan(o["face"][:, 0])
+        gh = ~np.isnan(g["face"][:, 0])
+        bad = np.nonzero(ok & (has != gh))[0]
+        assert bad.size == 0, f"{label}: exit point presence differs at {bad[:10]}"
+        sel = ok & has
+        ferr = np.abs(g["face"] - o["face"]).max(axis=1)
+        ftol = 2.0 * tol * np.maximum(1.0, np.nan_to_num(o["face_cond"], nan=1.0)) + 1e-6
+        bad = np.nonzero(sel & (ferr > ftol))[0]
+        assert bad.size == 0, (f"{label}: exit point error {ferr[bad[:5]]} > {np.broadcast_to(ftol, ferr.shape)[bad[:5]]}"
+                               f" at {bad[:5]}")
+        res["exit_points"] = int(sel.sum())
+        res["exit_max_err"] = float(ferr[sel].max()) if sel.any() else 0.0
+    return res
 
 
 def oracle_lattice(field, times, n, stride, N, mode=oracle.LINEAR, ids=None, jac=False, nthreads=0):

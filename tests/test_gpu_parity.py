@@ -67,10 +67,20 @@ def test_uniform_flow_closed_form_on_gpu():
     times = np.concatenate([[0.25], 0.25 + np.cumsum(rng.uniform(0.1, 0.5, N))])
     u = np.array([0.7, -0.3, 0.45])
     s = fields.uniform_flow(n, u, times)
-    g = run_gpu(n, _dev(s.grids("f32"), "f32"), times, stride=3)
+    g = run_gpu(n, _dev(s.grids("f32"), "f32"), times, stride=3, record_exit=True)
     o = oracle.flowmap(oracle.Field(n, s.grids("f32")), times, oracle.seed_lattice(n, 3), N)
-    compare(g, o, label="uniform")
+    res = compare(g, o, label="uniform")
     assert g["stats"]["particle_steps"] == int(np.where(o["flag"] == 0, N, o["exit"] + 1).sum())
+    # exit points: where the straight line x0 + u t leaves the box
+    seeds = oracle.seed_lattice(n, 3)
+    hi = np.array(n, dtype=float) - 1
+    t_face = np.where(u > 0, (hi - seeds) / u, np.where(u < 0, -seeds / u, np.inf))
+    t_sorted = np.sort(t_face, axis=1)
+    term = (g["flag"] == oracle.TERMINATED) & (t_sorted[:, 1] - t_sorted[:, 0] > 1e-6)
+    line = seeds + u * t_sorted[:, :1]
+    assert term.sum() > 100 and res["exit_points"] > 100
+    np.testing.assert_allclose(g["face"][term], line[term], atol=1e-5)
+    assert np.all(np.isnan(g["face"][g["flag"] == oracle.VALID]))
 
 
 def test_solid_body_rotation_on_gpu():
@@ -97,7 +107,7 @@ def test_double_gyre_full_parity():
     _say(f"{wl.name} full")
     s = wl.make_field()
     gr = s.grids("f32")
-    g = run_gpu(wl.n, _dev(gr, "f32"), s.times, stride=wl.stride)
+    g = run_gpu(wl.n, _dev(gr, "f32"), s.times, stride=wl.stride, record_exit=True)
     _, o = oracle_lattice(oracle.Field(wl.n, gr), s.times, wl.n, wl.stride, wl.n_steps)
     res = compare(g, o, label=wl.name)
     assert 0.15 < res["terminated"] < 0.35
@@ -139,7 +149,7 @@ def test_ragged_block_and_lattice_all_dtypes():
     for dt in ("f32", "f16", "bf16"):
         _say(f"ragged 37x23x19 stride 3 {dt}")
         gr = s.grids(dt)
-        g = run_gpu(n, _dev(gr, dt), s.times, stride=3)
+        g = run_gpu(n, _dev(gr, dt), s.times, stride=3, record_exit=True)
         _, o = oracle_lattice(oracle.Field(n, gr, dtype=dt), s.times, n, 3, N)
         res = compare(g, o, label=dt)
         assert 0.0 < res["terminated"] < 1.0
@@ -155,18 +165,20 @@ def test_explicit_seeds_including_outside_and_permutation():
     seeds[:10] = [[0, 0, 0], [23, 23, 23], [23, 0, 11.5], [-1e-9, 3, 3], [3, 23.0000001, 3],
                   [11.5, 11.5, 11.5], [0.5, 0.5, 0.5], [22.5, 22.5, 22.5], [5, 5, 23], [23, 5, 5]]
     _say("explicit seeds 3000 (with outside)")
-    g = run_gpu(n, _dev(gr, "f32"), s.times, seeds=seeds)
+    g = run_gpu(n, _dev(gr, "f32"), s.times, seeds=seeds, record_exit=True)
     o = oracle.flowmap(oracle.Field(n, gr), s.times, seeds, N)
     compare(g, o, label="explicit")
     outside = ~np.all((seeds >= 0) & (seeds <= 23), axis=1)
     assert np.all(g["flag"][outside] == 1) and np.all(g["exit"][outside] == 0)
     assert np.array_equal(g["end"][outside], seeds[outside])
+    assert np.all(np.isnan(g["face"][outside]))  # no exit point for seeds outside the block
     perm = rng.permutation(len(seeds))
     _say("explicit seeds permuted")
-    gp = run_gpu(n, _dev(gr, "f32"), s.times, seeds=seeds[perm])
+    gp = run_gpu(n, _dev(gr, "f32"), s.times, seeds=seeds[perm], record_exit=True)
     assert np.array_equal(gp["flag"], g["flag"][perm])
     assert np.array_equal(gp["exit"], g["exit"][perm])
     assert np.array_equal(gp["end"], g["end"][perm])
+    assert np.array_equal(gp["face"], g["face"][perm], equal_nan=True)
 
 
 def test_world_coordinates_origin_and_spacing():
@@ -179,11 +191,12 @@ def test_world_coordinates_origin_and_spacing():
     # a grid in world units per time: cell velocity times spacing
     grw = [(quant.promote(g, "f32") * spacing).astype(np.float32) for g in gr]
     _say("origin/spacing 20x16x12")
-    g = run_gpu(n, _dev(grw, "f32"), s.times, stride=2, origin=origin, spacing=spacing)
+    g = run_gpu(n, _dev(grw, "f32"), s.times, stride=2, origin=origin, spacing=spacing, record_exit=True)
     cells = [(quant.promote(g2, "f32") / spacing) for g2 in grw]
     _, o = oracle_lattice(oracle.Field(n, cells), s.times, n, 2, N)
     g_cells = dict(g)
     g_cells["end"] = (g["end"] - origin) / spacing
+    g_cells["face"] = (g["face"] - origin) / spacing
     compare(g_cells, o, label="world")
     np.testing.assert_allclose((g["seed"] - origin) / spacing, oracle.seed_lattice(n, 2), atol=0)
 
@@ -270,7 +283,7 @@ def test_rebin_between_launches_keeps_results():
     os.environ["BTO_REBIN_EVERY"] = "4"
     try:
         b = run_gpu(n, dev, s.times, stride=2)
-        c = run_gpu(n, dev, s.times, stride=2, chunks=[3, 9, 1, 17])
+        c = run_gpu(n, dev, s.times, stride=2, chunks=[3, 9, 1, 17], record_exit=True)
     finally:
         del os.environ["BTO_REBIN_EVERY"]
     _, o = oracle_lattice(oracle.Field(n, gr), s.times, n, 2, N)
@@ -300,7 +313,7 @@ def test_two_lanes_per_particle_matches_oracle_and_one_lane():
     a = run_gpu(n, dev, s.times, seeds=seeds)
     b = run_gpu(n, dev, s.times, seeds=seeds, tuning=dict(lanes_per_particle=2))
     c = run_gpu(n, dev, s.times, seeds=seeds, chunks=[3, 9, 1, 17],
-                tuning=dict(lanes_per_particle=2, rebin_every=4, steps_per_launch=7))
+                tuning=dict(lanes_per_particle=2, rebin_every=4, steps_per_launch=7), record_exit=True)
     o = oracle.flowmap(oracle.Field(n, gr), s.times, seeds, N)
     amb = o["margin"] < 1e-6
     for r, lab in ((b, "2 lanes"), (c, "2 lanes, rebin, ragged calls")):
@@ -310,6 +323,42 @@ def test_two_lanes_per_particle_matches_oracle_and_one_lane():
         assert np.abs(r["end"] - a["end"]).max() < 5e-6
         assert r["n_valid"] == int((r["flag"] == 0).sum())
         assert r["stats"]["particle_steps"] == a["stats"]["particle_steps"] or amb.any()
+
+
+def test_exit_points_only_for_calls_that_record_them():
+    """Exit points are kept for particles terminated by a call made with
+    BTO_RECORD_EXIT; particles terminated by other calls (and every seed
+    before any call) read NaN.  Recording changes nothing else."""
+    import torch
+    from paper_2004_02003_amd import Context
+
+    n = (20, 20, 20)
+    N = 30
+    rng = np.random.default_rng(7)
+    times = np.concatenate([[0.25], 0.25 + np.cumsum(rng.uniform(0.1, 0.5, N))])
+    s = fields.uniform_flow(n, np.array([0.7, -0.3, 0.45]), times)
+    dev = _dev(s.grids("f32"), "f32")
+    o = oracle.flowmap(oracle.Field(n, s.grids("f32")), times, oracle.seed_lattice(n, 3), N)
+    _say("exit points: recording calls only")
+    plain = run_gpu(n, dev, times, stride=3)
+    with Context(n, len(o["flag"])) as ctx:
+        ctx.seed(3)
+        assert torch.isnan(ctx.exit_points()).all()
+        ctx.advect(dev[:11], times[:11], record_exit=True)    # steps 0..9 record
+        ctx.advect(dev[10:], times[10:], record_exit=False)  # steps 10..29 do not
+        fm = ctx.flowmap()
+        face = ctx.exit_points().cpu().numpy()
+        g = {k: v.cpu().numpy() for k, v in fm.items()}
+    # same events; positions agree to the FP32 repacking at the call boundary
+    safe = o["margin"] >= 1e-6
+    assert np.array_equal(g["flag"][safe], plain["flag"][safe]) and np.array_equal(g["exit"][safe], plain["exit"][safe])
+    assert np.abs(g["end"] - plain["end"]).max() < 5e-6
+    early = (g["flag"] == oracle.TERMINATED) & (g["exit"] < 10)
+    late = (g["flag"] == oracle.TERMINATED) & (g["exit"] >= 10)
+    assert early.sum() > 20 and late.sum() > 20
+    assert np.all(np.isnan(face[late])) and np.all(np.isnan(face[g["flag"] == oracle.VALID]))
+    ok = early & (o["margin"] >= 1e-6)
+    np.testing.assert_allclose(face[ok], o["face"][ok], atol=3e-5)
 
 
 def test_error_paths_and_tuning_through_the_c_abi():

@@ -64,7 +64,7 @@ def test_create_rejects_bad_blocks_before_touching_a_device(lib):
     for fn, args in [("bto_seed", (None, 2, None, None, None)),
                      ("bto_advect_interval", (None, None, None, 1, 0, 0, None)),
                      ("bto_flowmap_out", (None, None, None, None, None, None, None)),
-                     ("bto_stats", (None, None, None)),
+                     ("bto_stats", (None, None, None)), ("bto_exit_points", (None, None, None)),
                      ("bto_set_tuning", (None, None)), ("bto_get_tuning", (None, None)),
                      ("bto_adjoint_interval", (None, None, None, 1, 0, 0, None, 1, None, None, None, 1, None)),
                      ("bto_ftle", (None, None, 0, 1.0, None, None))]:
