@@ -211,6 +211,40 @@ int bto_adjoint_interval(bto_ctx *ctx, const void *const *d_fields, const double
  * sigma = ln sqrt(lambda_max(J^T J)) / |T| (d_jac: n x 9 floats, d_out: n floats). */
 int bto_ftle(bto_ctx *ctx, const float *d_jac, int64_t n, double T, float *d_out, void *stream);
 
+/* ---- Post hoc side of the seed-lattice flow map (no context needed) ---- */
+
+/* Place one block's seed-ordered flow map (lattice mb[3] points per axis, x
+ * fastest: d_src_xyz mb0*mb1*mb2 x 3 doubles, d_src_flag bytes) into a larger
+ * lattice of M[3] points at lattice offset off[3] (d_dst_xyz, d_dst_flag, same
+ * layout), adding shift3 (host, 3 doubles, may be NULL) to every position, so
+ * that the flow maps of neighbouring blocks form one lattice in one frame.
+ * Device pointers; async on `stream`.  BTO_EINVAL if the block does not fit. */
+int bto_place_block(const int32_t mb[3], const int32_t M[3], const int32_t off[3], const double *shift3,
+                    const double *d_src_xyz, const uint8_t *d_src_flag, double *d_dst_xyz, uint8_t *d_dst_flag,
+                    void *stream);
+
+/* Rebuild the terminated entries of a lattice flow map (Section 3.2): every
+ * entry whose d_flag is not BTO_VALID is replaced by the linear interpolation
+ * of Eq. (1) between the nearest valid entries on both sides of it along one
+ * lattice line (Eq. (2): the rebuilt value changes no later linear
+ * interpolation).  Lines are taken one axis at a time, x then y then z; a pass
+ * may use values rebuilt by an earlier pass, never values rebuilt in the same
+ * pass.  m[3]: lattice points per axis (x fastest); d_end_xyz: m0*m1*m2 x 3
+ * doubles, updated in place (entries left unrebuilt become NaN); d_state:
+ * bytes out, 0 missing, 1 valid, 2 rebuilt.  Device pointers; async. */
+int bto_reconstruct_lattice(const int32_t m[3], double *d_end_xyz, const uint8_t *d_flag, uint8_t *d_state,
+                            void *stream);
+
+/* Accuracy of a BTO flow map b against a communicating one m (Section 4,
+ * Eq. (5) and Eq. (6)): over the n entries that m keeps (d_m_flag BTO_VALID)
+ * and b covers (d_b_state nonzero), out5[0] = mean |b - m| (the total average
+ * L2 norm), out5[1] = maximum |b - m|, out5[2] = entries compared, out5[3] =
+ * entries m keeps that b leaves missing, out5[4] = (cell - mean) / cell * 100
+ * (Accuracy%, cell = the grid cell side in the same units).  out5 is host
+ * memory; synchronizes `stream`.  Deterministic for a given n. */
+int bto_flowmap_error(int64_t n, const double *d_b_xyz, const uint8_t *d_b_state, const double *d_m_xyz,
+                      const uint8_t *d_m_flag, double cell, double *out5, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

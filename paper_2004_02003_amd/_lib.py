@@ -23,7 +23,8 @@ BTO_VALID, BTO_TERMINATED, BTO_INVALID = 0, 1, 2
 EXPORTED = [
     "bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
     "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle",
-    "bto_set_tuning", "bto_get_tuning", "bto_exit_points",
+    "bto_set_tuning", "bto_get_tuning", "bto_exit_points", "bto_place_block", "bto_reconstruct_lattice",
+    "bto_flowmap_error",
 ]
 
 _ERRNAMES = {BTO_EINVAL: "BTO_EINVAL", BTO_ENOMEM: "BTO_ENOMEM", BTO_EHIP: "BTO_EHIP",
@@ -74,6 +75,11 @@ def load() -> ctypes.CDLL:
     L.bto_advect_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp]
     L.bto_flowmap_out.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
     L.bto_exit_points.argtypes = [vp, vp, vp]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.bto_place_block.argtypes = [i32p, i32p, i32p, ctypes.POINTER(ctypes.c_double), vp, vp, vp, vp, vp]
+    L.bto_reconstruct_lattice.argtypes = [i32p, vp, vp, vp, vp]
+    L.bto_flowmap_error.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_double), vp]
     L.bto_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
     L.bto_adjoint_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
     L.bto_ftle.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]

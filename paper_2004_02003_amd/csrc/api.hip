@@ -460,6 +460,48 @@ int bto_exit_points(bto_ctx* c, double* d_exit_xyz, void* stream) {
     return BTO_OK;
 }
 
+static bool lattice_ok(const int32_t m[3]) {
+    return m && m[0] >= 1 && m[1] >= 1 && m[2] >= 1 && (int64_t)m[0] * m[1] * m[2] <= ((int64_t)1 << 40);
+}
+
+int bto_reconstruct_lattice(const int32_t m[3], double* d_end_xyz, const uint8_t* d_flag, uint8_t* d_state,
+                            void* stream) {
+    if (!lattice_ok(m) || !d_end_xyz || !d_flag || !d_state) return BTO_EINVAL;
+    return launch_reconstruct(m, d_end_xyz, d_flag, d_state, (hipStream_t)stream) == hipSuccess ? BTO_OK : BTO_EHIP;
+}
+
+int bto_flowmap_error(int64_t n, const double* d_b_xyz, const uint8_t* d_b_state, const double* d_m_xyz,
+                      const uint8_t* d_m_flag, double cell, double* out5, void* stream) {
+    if (n < 1 || !d_b_xyz || !d_b_state || !d_m_xyz || !d_m_flag || !out5 || !(cell > 0.0)) return BTO_EINVAL;
+    void* scratch = nullptr;
+    if (hipMalloc(&scratch, err_scratch_bytes(n)) != hipSuccess) return BTO_ENOMEM;
+    double r[4];
+    const hipError_t e = launch_flowmap_error(n, d_b_xyz, d_b_state, d_m_xyz, d_m_flag, scratch, r, (hipStream_t)stream);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return BTO_EHIP;
+    const double mean = r[2] > 0 ? r[0] / r[2] : 0.0;
+    out5[0] = mean;
+    out5[1] = r[1];
+    out5[2] = r[2];
+    out5[3] = r[3];
+    out5[4] = (cell - mean) / cell * 100.0;
+    return BTO_OK;
+}
+
+int bto_place_block(const int32_t mb[3], const int32_t M[3], const int32_t off[3], const double shift3[3],
+                    const double* d_src_xyz, const uint8_t* d_src_flag, double* d_dst_xyz, uint8_t* d_dst_flag,
+                    void* stream) {
+    if (!lattice_ok(mb) || !lattice_ok(M) || !off || !d_src_xyz || !d_src_flag || !d_dst_xyz || !d_dst_flag)
+        return BTO_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (off[d] < 0 || off[d] + mb[d] > M[d]) return BTO_EINVAL;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    return launch_place(mb, M, off, shift3 ? shift3 : zero, d_src_xyz, d_src_flag, d_dst_xyz, d_dst_flag,
+                        (hipStream_t)stream) == hipSuccess
+               ? BTO_OK
+               : BTO_EHIP;
+}
+
 int bto_stats(bto_ctx* c, bto_stats_t* out, void* stream) {
     int rc = begin(c);
     if (rc) return rc;

@@ -131,6 +131,13 @@ hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, un
 hipError_t launch_advect(const AdvectArgs& a, int dtype, int mode, int lanes_per_particle, int record_exit,
                          int blocks_per_seg, hipStream_t s);
 hipError_t launch_exit_points(const FlowmapArgs& a, hipStream_t s);
+hipError_t launch_reconstruct(const int32_t m[3], double* end, const uint8_t* flag, uint8_t* state, hipStream_t s);
+size_t err_scratch_bytes(int64_t P);
+hipError_t launch_flowmap_error(int64_t P, const double* b, const uint8_t* bstate, const double* m, const uint8_t* mflag,
+                                void* scratch, double out4[4], hipStream_t s);
+hipError_t launch_place(const int32_t mb[3], const int32_t M[3], const int32_t off[3], const double shift[3],
+                        const double* src_xyz, const uint8_t* src_flag, double* dst_xyz, uint8_t* dst_flag,
+                        hipStream_t s);
 hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t s);
 int advect_max_blocks_per_cu(int dtype, int mode, int lanes_per_particle, int record_exit);
 hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);

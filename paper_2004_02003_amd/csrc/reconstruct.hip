@@ -1,0 +1,200 @@
+// Post hoc side of the flow map on the seed lattice: placing per-block flow
+// maps into one lattice, rebuilding terminated entries by the one-dimensional
+// linear interpolation of Eq. (1) (Section 3.2; Eq. (2) shows the rebuilt
+// value changes no later linear interpolation), and the accuracy metric of
+// Eq. (5) and Eq. (6) (Section 4).
+//
+// Layout: lattice entries in x-fastest order, end positions as 3 doubles per
+// entry, states as bytes (0 missing, 1 known, 2 rebuilt).  The rebuild runs
+// one pass per axis (x, then y, then z); a pass gives each lattice line to one
+// thread, which walks it once and fills every run of unknown entries that has
+// known entries on both sides.  Lines of one pass are disjoint, so a pass
+// needs no synchronisation beyond the kernel boundary.
+#include "bto_internal.h"
+
+namespace bto {
+
+constexpr uint8_t ST_MISSING = 0, ST_KNOWN = 1, ST_REBUILT = 2;
+
+__global__ __launch_bounds__(BLOCK) void recon_init_kernel(int64_t P, double* end, const uint8_t* flag,
+                                                           uint8_t* state) {
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < P; t += (int64_t)gridDim.x * BLOCK) {
+        const bool known = flag[t] == (uint8_t)S_VALID;
+        state[t] = known ? ST_KNOWN : ST_MISSING;
+        if (!known) {
+            const double nan = __builtin_nan("");
+            end[3 * t] = nan;
+            end[3 * t + 1] = nan;
+            end[3 * t + 2] = nan;
+        }
+    }
+}
+
+// One pass along the lattice axis with point stride `st` and length `len`;
+// lines are indexed by the other two axes (counts n_a, n_b, strides s_a, s_b).
+__global__ __launch_bounds__(BLOCK) void recon_pass_kernel(int64_t n_lines, int32_t n_a, int64_t s_a, int64_t s_b,
+                                                           int32_t len, int64_t st, double* end, uint8_t* state) {
+#pragma clang fp contract(off)  // Eq. (1) rounded as written: two products, one sum
+    const int64_t line = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (line >= n_lines) return;
+    const int64_t a = line % n_a, b = line / n_a;
+    const int64_t base = a * s_a + b * s_b;
+    int32_t i0 = -1;
+    double f0[3] = {0.0, 0.0, 0.0};
+    for (int32_t i = 0; i < len; ++i) {
+        const int64_t q = base + (int64_t)i * st;
+        if (state[q] == ST_MISSING) continue;
+        const double f2[3] = {end[3 * q], end[3 * q + 1], end[3 * q + 2]};
+        if (i0 >= 0 && i > i0 + 1) {
+            const double span = (double)(i - i0);
+            for (int32_t k = i0 + 1; k < i; ++k) {
+                // Eq. (1): L(x1) = (x1 - x0)/(x2 - x0) f(x2) + (x2 - x1)/(x2 - x0) f(x0)
+                const double w2 = (double)(k - i0) / span;
+                const double w0 = (double)(i - k) / span;
+                const int64_t r = base + (int64_t)k * st;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) end[3 * r + d] = w2 * f2[d] + w0 * f0[d];
+                state[r] = ST_REBUILT;
+            }
+        }
+        i0 = i;
+        f0[0] = f2[0];
+        f0[1] = f2[1];
+        f0[2] = f2[2];
+    }
+}
+
+// Eq. (5) partial sums: per workgroup the sum and maximum of |b - m| over the
+// entries m keeps (flag valid) and b covers, and the counts of covered and
+// uncovered such entries.
+struct ErrPart {
+    double sum, max;
+    unsigned long long n, uncovered;
+};
+
+__global__ __launch_bounds__(BLOCK) void err_partial_kernel(int64_t P, const double* b, const uint8_t* bstate,
+                                                            const double* m, const uint8_t* mflag, ErrPart* part) {
+    double sum = 0.0, mx = 0.0;
+    unsigned long long n = 0, unc = 0;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < P; t += (int64_t)gridDim.x * BLOCK) {
+        if (mflag[t] != (uint8_t)S_VALID) continue;
+        if (bstate[t] == ST_MISSING) {
+            ++unc;
+            continue;
+        }
+        const double dx = b[3 * t] - m[3 * t], dy = b[3 * t + 1] - m[3 * t + 1], dz = b[3 * t + 2] - m[3 * t + 2];
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        sum += d;
+        mx = fmax(mx, d);
+        ++n;
+    }
+    __shared__ double s_sum[BLOCK], s_max[BLOCK];
+    __shared__ unsigned long long s_n[BLOCK], s_u[BLOCK];
+    s_sum[threadIdx.x] = sum;
+    s_max[threadIdx.x] = mx;
+    s_n[threadIdx.x] = n;
+    s_u[threadIdx.x] = unc;
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s_sum[threadIdx.x] += s_sum[threadIdx.x + o];
+            s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + o]);
+            s_n[threadIdx.x] += s_n[threadIdx.x + o];
+            s_u[threadIdx.x] += s_u[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = ErrPart{s_sum[0], s_max[0], s_n[0], s_u[0]};
+}
+
+// Fixed-order sum of the partials (deterministic for a given grid).
+__global__ void err_final_kernel(int nparts, const ErrPart* part, ErrPart* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    ErrPart r{0.0, 0.0, 0ull, 0ull};
+    for (int i = 0; i < nparts; ++i) {
+        r.sum += part[i].sum;
+        r.max = fmax(r.max, part[i].max);
+        r.n += part[i].n;
+        r.uncovered += part[i].uncovered;
+    }
+    *out = r;
+}
+
+// Copy a block's seed-ordered flow map (lattice mb, x fastest) into a larger
+// lattice M at lattice offset off, adding `shift` to the positions (block
+// coordinates -> domain coordinates).
+__global__ __launch_bounds__(BLOCK) void place_kernel(int32_t mb0, int32_t mb1, int64_t Pb, int32_t M0, int32_t M1,
+                                                      int32_t o0, int32_t o1, int32_t o2, double sh0, double sh1,
+                                                      double sh2, const double* src_xyz, const uint8_t* src_flag,
+                                                      double* dst_xyz, uint8_t* dst_flag) {
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < Pb; t += (int64_t)gridDim.x * BLOCK) {
+        const int64_t i = t % mb0, j = (t / mb0) % mb1, k = t / ((int64_t)mb0 * mb1);
+        const int64_t q = (i + o0) + (int64_t)M0 * ((j + o1) + (int64_t)M1 * (k + o2));
+        dst_xyz[3 * q] = src_xyz[3 * t] + sh0;
+        dst_xyz[3 * q + 1] = src_xyz[3 * t + 1] + sh1;
+        dst_xyz[3 * q + 2] = src_xyz[3 * t + 2] + sh2;
+        dst_flag[q] = src_flag[t];
+    }
+}
+
+static int grid_for(int64_t n) {
+    const int64_t nb = (n + BLOCK - 1) / BLOCK;
+    return (int)(nb < 4096 ? (nb > 0 ? nb : 1) : 4096);
+}
+
+hipError_t launch_reconstruct(const int32_t m[3], double* end, const uint8_t* flag, uint8_t* state, hipStream_t s) {
+    const int64_t P = (int64_t)m[0] * m[1] * m[2];
+    hipLaunchKernelGGL(recon_init_kernel, dim3(grid_for(P)), dim3(BLOCK), 0, s, P, end, flag, state);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t sx = 1, sy = m[0], sz = (int64_t)m[0] * m[1];
+    // x pass: lines over (y, z); y pass: lines over (x, z); z pass: lines over (x, y)
+    struct Pass { int32_t len; int64_t st; int32_t n_a; int64_t s_a; int32_t n_b; int64_t s_b; };
+    const Pass passes[3] = {{m[0], sx, m[1], sy, m[2], sz}, {m[1], sy, m[0], sx, m[2], sz}, {m[2], sz, m[0], sx, m[1], sy}};
+    for (const Pass& p : passes) {
+        const int64_t lines = (int64_t)p.n_a * p.n_b;
+        if (p.len < 3 || lines == 0) continue;
+        const int64_t nb = (lines + BLOCK - 1) / BLOCK;
+        hipLaunchKernelGGL(recon_pass_kernel, dim3((unsigned)nb), dim3(BLOCK), 0, s, lines, p.n_a, p.s_a, p.s_b, p.len,
+                           p.st, end, state);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int err_parts_for(int64_t P) { return grid_for(P) < 1024 ? grid_for(P) : 1024; }
+
+size_t err_scratch_bytes(int64_t P) { return sizeof(ErrPart) * (size_t)(err_parts_for(P) + 1); }
+
+hipError_t launch_flowmap_error(int64_t P, const double* b, const uint8_t* bstate, const double* m, const uint8_t* mflag,
+                                void* scratch, double out4[4], hipStream_t s) {
+    const int parts = err_parts_for(P);
+    ErrPart* part = static_cast<ErrPart*>(scratch);
+    hipLaunchKernelGGL(err_partial_kernel, dim3(parts), dim3(BLOCK), 0, s, P, b, bstate, m, mflag, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(err_final_kernel, dim3(1), dim3(64), 0, s, parts, part, part + parts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ErrPart r;
+    e = hipMemcpyAsync(&r, part + parts, sizeof r, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    out4[0] = r.sum;
+    out4[1] = r.max;
+    out4[2] = (double)r.n;
+    out4[3] = (double)r.uncovered;
+    return hipSuccess;
+}
+
+hipError_t launch_place(const int32_t mb[3], const int32_t M[3], const int32_t off[3], const double shift[3],
+                        const double* src_xyz, const uint8_t* src_flag, double* dst_xyz, uint8_t* dst_flag,
+                        hipStream_t s) {
+    const int64_t Pb = (int64_t)mb[0] * mb[1] * mb[2];
+    hipLaunchKernelGGL(place_kernel, dim3(grid_for(Pb)), dim3(BLOCK), 0, s, mb[0], mb[1], Pb, M[0], M[1], off[0], off[1],
+                       off[2], shift[0], shift[1], shift[2], src_xyz, src_flag, dst_xyz, dst_flag);
+    return hipGetLastError();
+}
+
+}  // namespace bto
