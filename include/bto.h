@@ -231,7 +231,8 @@ int bto_place_block(const int32_t mb[3], const int32_t M[3], const int32_t off[3
  * may use values rebuilt by an earlier pass, never values rebuilt in the same
  * pass.  m[3]: lattice points per axis (x fastest); d_end_xyz: m0*m1*m2 x 3
  * doubles, updated in place (entries left unrebuilt become NaN); d_state:
- * bytes out, 0 missing, 1 valid, 2 rebuilt.  Device pointers; async. */
+ * bytes out, 0 missing, 1 valid, 2 rebuilt.  Device pointers; async.
+ * BTO_EINVAL for null pointers or more than 1024 lattice points on an axis. */
 int bto_reconstruct_lattice(const int32_t m[3], double *d_end_xyz, const uint8_t *d_flag, uint8_t *d_state,
                             void *stream);
 

@@ -467,6 +467,7 @@ static bool lattice_ok(const int32_t m[3]) {
 int bto_reconstruct_lattice(const int32_t m[3], double* d_end_xyz, const uint8_t* d_flag, uint8_t* d_state,
                             void* stream) {
     if (!lattice_ok(m) || !d_end_xyz || !d_flag || !d_state) return BTO_EINVAL;
+    if (m[0] > 1024 || m[1] > 1024 || m[2] > 1024) return BTO_EINVAL;  // one line fits one wavefront's chunks
     return launch_reconstruct(m, d_end_xyz, d_flag, d_state, (hipStream_t)stream) == hipSuccess ? BTO_OK : BTO_EHIP;
 }
 

@@ -7,9 +7,9 @@
 // Layout: lattice entries in x-fastest order, end positions as 3 doubles per
 // entry, states as bytes (0 missing, 1 known, 2 rebuilt).  The rebuild runs
 // one pass per axis (x, then y, then z); a pass gives each lattice line to one
-// thread, which walks it once and fills every run of unknown entries that has
-// known entries on both sides.  Lines of one pass are disjoint, so a pass
-// needs no synchronisation beyond the kernel boundary.
+// wavefront, which fills every run of unknown entries that has known entries
+// on both sides.  Lines of one pass are disjoint, so a pass needs no
+// synchronisation beyond the kernel boundary.
 #include "bto_internal.h"
 
 namespace bto {
@@ -30,37 +30,70 @@ __global__ __launch_bounds__(BLOCK) void recon_init_kernel(int64_t P, double* en
     }
 }
 
-// One pass along the lattice axis with point stride `st` and length `len`;
-// lines are indexed by the other two axes (counts n_a, n_b, strides s_a, s_b).
+// One pass along the lattice axis with point stride `st` and length `len`
+// (at most 1024: a lattice line never exceeds the grid's points per axis);
+// lines are indexed by the other two axes (count n_a along the first, strides
+// s_a, s_b).  One wavefront per line: the line is read in chunks of 64
+// entries, a ballot per chunk marks the known ones, and every unknown entry
+// finds its nearest known neighbours from the ballot masks (below: highest set
+// bit under its lane, carried across chunks left to right; above: lowest set
+// bit over its lane, carried right to left).  All states are read before any
+// entry is written, so only entries known at the start of the pass bracket.
+constexpr int LINE_CHUNKS = 16;  // 16 x 64 = 1024 entries
+
 __global__ __launch_bounds__(BLOCK) void recon_pass_kernel(int64_t n_lines, int32_t n_a, int64_t s_a, int64_t s_b,
                                                            int32_t len, int64_t st, double* end, uint8_t* state) {
 #pragma clang fp contract(off)  // Eq. (1) rounded as written: two products, one sum
-    const int64_t line = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (line >= n_lines) return;
+    const int64_t line = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (line >= n_lines) return;  // whole wavefronts leave together
     const int64_t a = line % n_a, b = line / n_a;
     const int64_t base = a * s_a + b * s_b;
-    int32_t i0 = -1;
-    double f0[3] = {0.0, 0.0, 0.0};
-    for (int32_t i = 0; i < len; ++i) {
-        const int64_t q = base + (int64_t)i * st;
-        if (state[q] == ST_MISSING) continue;
-        const double f2[3] = {end[3 * q], end[3 * q + 1], end[3 * q + 2]};
-        if (i0 >= 0 && i > i0 + 1) {
-            const double span = (double)(i - i0);
-            for (int32_t k = i0 + 1; k < i; ++k) {
-                // Eq. (1): L(x1) = (x1 - x0)/(x2 - x0) f(x2) + (x2 - x1)/(x2 - x0) f(x0)
-                const double w2 = (double)(k - i0) / span;
-                const double w0 = (double)(i - k) / span;
-                const int64_t r = base + (int64_t)k * st;
+    const int nchunk = (len + WAVE - 1) / WAVE;
+    unsigned long long mask[LINE_CHUNKS];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) end[3 * r + d] = w2 * f2[d] + w0 * f0[d];
-                state[r] = ST_REBUILT;
-            }
+    for (int c = 0; c < LINE_CHUNKS; ++c) {
+        mask[c] = 0ull;
+        if (c < nchunk) {
+            const int i = c * WAVE + lane;
+            const bool known = i < len && state[base + (int64_t)i * st] != ST_MISSING;
+            mask[c] = __ballot(known);
         }
-        i0 = i;
-        f0[0] = f2[0];
-        f0[1] = f2[1];
-        f0[2] = f2[2];
+    }
+    // nearest known index below each of this lane's entries (-1: none)
+    int lo[LINE_CHUNKS];
+    int carry = -1;
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int c = 0; c < LINE_CHUNKS; ++c) {
+        lo[c] = -1;
+        if (c < nchunk) {
+            const unsigned long long m = mask[c] & below;
+            lo[c] = m ? c * WAVE + 63 - __clzll((long long)m) : carry;
+            if (mask[c]) carry = c * WAVE + 63 - __clzll((long long)mask[c]);
+        }
+    }
+    // nearest known index above, then Eq. (1) for the unknown entries between
+    carry = -1;
+    const unsigned long long above = lane == 63 ? 0ull : ~((2ull << lane) - 1ull);
+#pragma unroll
+    for (int c = LINE_CHUNKS - 1; c >= 0; --c) {
+        if (c >= nchunk) continue;
+        const unsigned long long m = mask[c] & above;
+        const int hi = m ? c * WAVE + __ffsll((long long)m) - 1 : carry;
+        if (mask[c]) carry = c * WAVE + __ffsll((long long)mask[c]) - 1;
+        const int i = c * WAVE + lane;
+        const bool missing = i < len && !((mask[c] >> lane) & 1ull);
+        if (missing && lo[c] >= 0 && hi >= 0) {
+            // Eq. (1): L(x1) = (x1 - x0)/(x2 - x0) f(x2) + (x2 - x1)/(x2 - x0) f(x0)
+            const double span = (double)(hi - lo[c]);
+            const double w2 = (double)(i - lo[c]) / span;
+            const double w0 = (double)(hi - i) / span;
+            const int64_t q0 = base + (int64_t)lo[c] * st, q2 = base + (int64_t)hi * st, r = base + (int64_t)i * st;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) end[3 * r + d] = w2 * end[3 * q2 + d] + w0 * end[3 * q0 + d];
+            state[r] = ST_REBUILT;
+        }
     }
 }
 
@@ -154,7 +187,8 @@ hipError_t launch_reconstruct(const int32_t m[3], double* end, const uint8_t* fl
     for (const Pass& p : passes) {
         const int64_t lines = (int64_t)p.n_a * p.n_b;
         if (p.len < 3 || lines == 0) continue;
-        const int64_t nb = (lines + BLOCK - 1) / BLOCK;
+        if (p.len > LINE_CHUNKS * WAVE) return hipErrorInvalidValue;
+        const int64_t nb = (lines * WAVE + BLOCK - 1) / BLOCK;  // one wavefront per line
         hipLaunchKernelGGL(recon_pass_kernel, dim3((unsigned)nb), dim3(BLOCK), 0, s, lines, p.n_a, p.s_a, p.s_b, p.len,
                            p.st, end, state);
         e = hipGetLastError();

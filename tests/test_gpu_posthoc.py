@@ -40,7 +40,8 @@ def _t(a):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
 
 
-@pytest.mark.parametrize("m", [(13, 7, 5), (1, 9, 4), (2, 2, 2), (40, 33, 17), (1, 1, 1)])
+@pytest.mark.parametrize("m", [(13, 7, 5), (1, 9, 4), (2, 2, 2), (40, 33, 17), (1, 1, 1), (200, 3, 2),
+                               (3, 130, 2), (2, 3, 1024), (64, 64, 65)])
 def test_reconstruct_bit_exact_against_oracle(m):
     from paper_2004_02003_amd import posthoc
 
@@ -116,6 +117,9 @@ def test_place_block_bit_exact():
     from paper_2004_02003_amd import BTOError
     with pytest.raises(BTOError):
         posthoc.place_block(_t(src), _t(sflag), (3, 2, 1), dst, dflag, M, (8, 6, 5))  # does not fit
+    with pytest.raises(BTOError):
+        big = torch.zeros((1025 * 2, 3), dtype=torch.float64, device="cuda")
+        posthoc.reconstruct_lattice(big, torch.zeros(2050, dtype=torch.uint8, device="cuda"), (1025, 2, 1))
 
 
 def test_multiblock_bto_accuracy_end_to_end():
