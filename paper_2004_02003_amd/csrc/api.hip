@@ -211,7 +211,7 @@ static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hip
     return BTO_OK;
 }
 
-// Re-sort the live particles of every segment by brick (Morton) order.
+// Re-sort the live particles of every segment by 32x2x2-cell bin, bins in x-fastest order.
 static int rebin(bto_ctx* c, hipStream_t s) {
     uint32_t nb[3];
     for (int d = 0; d < 3; ++d) nb[d] = (uint32_t)((c->blk.n[d] + REBIN_BIN[d] - 1) / REBIN_BIN[d]);

@@ -1,6 +1,6 @@
 // Spatial re-sort of live particles ("rebin", part of particle management).
 //
-// Particles start brick-ordered, so the 64 lanes of a wavefront read nearby
+// Particles start in lattice order, so the 64 lanes of a wavefront read nearby
 // cells and share cache lines; as the flow disperses them that locality
 // decays and every lane touches its own lines.  Between advection launches the
 // live particles of each XCD segment are re-ordered by the 32x2x2-cell bin
@@ -8,12 +8,12 @@
 // along a few grid rows, so each of a cell's row loads covers long runs of
 // contiguous memory -- the same reason the lattice is seeded x-fastest), with
 // a counting sort:
-//   count   - per particle, atomically increment its (segment, brick) bin;
+//   count   - per particle, atomically increment its (segment, bin) counter;
 //             the old value is the particle's rank inside the bin;
 //   scan    - exclusive prefix sum over all bins (segment-major);
 //   scatter - move each particle to its segment base + bin offset + rank, and
 //             zero its bin for the next rebin.
-// Order inside a brick is unspecified; results do not depend on particle
+// Order inside a bin is unspecified; results do not depend on particle
 // order.
 #include <rocprim/device/device_scan.hpp>
 

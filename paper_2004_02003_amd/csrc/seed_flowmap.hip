@@ -9,10 +9,12 @@ namespace bto {
 // ---------------------------------------------------------------------------
 
 // Lattice points are stored brick-major: bricks of B0 x B1 x B2 = 64 lattice
-// points (one wavefront; default 16 x 2 x 2, x-elongated so that each of a
-// cell's four row loads covers a few long contiguous runs of the grid) in
-// x-fastest brick order, x-fastest inside a brick.  Bricks on the high faces
-// may be partial; slot(id) is the closed-form prefix count.
+// points (one wavefront) in x-fastest brick order, x-fastest inside a brick.
+// The default brick, 64 x 1 x 1, is the natural x-fastest lattice order: a
+// wavefront's lanes lie along one grid row, so each of a cell's four row loads
+// covers one long contiguous run of the grid (measured best for the gather).
+// Bricks on the high faces may be partial; slot(id) is the closed-form prefix
+// count.
 __device__ __forceinline__ int64_t brick_slot(const int32_t m[3], const int32_t B[3], int a, int b, int c) {
     const int bx = a / B[0], by = b / B[1], bz = c / B[2];
     const int lx = a % B[0], ly = b % B[1], lz = c % B[2];
