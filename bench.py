@@ -167,6 +167,52 @@ def posthoc_accuracy(log):
     return out
 
 
+def insitu_overlap(log, n=128, modes=32):
+    """The in situ driver fed by a running "simulation": every cycle the device
+    turbulence generator computes the next grid into the simulation's own
+    buffer (n^3 points, FP32) on the caller's stream, and the driver copies it
+    into its ring and advects (n/2)^3 particles one step.  Serial (copy and
+    advection on the caller's stream) vs overlapped (ingest and compute streams
+    of the driver's own, so the advection of step c runs beside the generation
+    of grid c+1).  Wall-clock ms per cycle over 50 cycles, best of 3, and the
+    generator alone for scale."""
+    import torch
+    from bto_inputs import _turb, fields
+    from paper_2004_02003_amd import Context, InSituDriver
+
+    ncyc = 51
+    s = fields.turbulence(n, modes, 2, ncyc, 0.02)
+    gen = _turb.DeviceTurbulence(s.lazy)
+    buf = torch.empty((n, n, n, 3), dtype=torch.float32, device="cuda")
+    out = {"workload": f"turbulence {n}^3, {modes} modes, f32, {n // 2}^3 seeds, 50 cycles"}
+
+    def wall(fn, reps=3):
+        best = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t0) / (ncyc - 1))
+        return round(1e3 * best, 4)
+
+    def gen_only():
+        for c in range(ncyc):
+            gen.fill(c, "f32", buf)
+    out["generator_only_ms_per_cycle"] = wall(gen_only)
+    for overlap in (False, True):
+        with Context((n, n, n), (n // 2) ** 3) as ctx:
+            def run():
+                drv = InSituDriver(ctx, interval=ncyc - 1, stride=2, copy=True, overlap=overlap, timing=False)
+                for c in range(ncyc):
+                    gen.fill(c, "f32", buf)
+                    drv.cycle(buf, float(s.times[c]))
+                drv.synchronize()
+            out[("overlapped" if overlap else "serial") + "_ms_per_cycle"] = wall(run)
+    log(f"in situ with a running simulation: {out}")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,6 +369,7 @@ def main(argv=None):
         ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
         result["insitu_per_cycle"] = {"value": round(psteps_interval / (ms * 1e-3), 1), "ms": round(ms, 4),
                                       "launches": N}
+
     ctx.close()
 
     # FP16 / BF16 storage of the same field, with the error against the FP64 oracle
@@ -372,6 +419,7 @@ def main(argv=None):
     if not args.no_variants and wl.name == "abc_128":
         result["paper_context"] = paper_context(log)
         result["posthoc_accuracy"] = posthoc_accuracy(log)
+        result["insitu_overlap"] = [insitu_overlap(log, 128, 32), insitu_overlap(log, 256, 64)]
 
     if not args.no_cpu_baseline:
         ids = np.arange(0, P, 1 if not turb else 1024)

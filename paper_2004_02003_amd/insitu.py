@@ -26,25 +26,38 @@ class InSituDriver:
 
     ``on_flowmap(index, flowmap, t0, t1)`` receives each finished interval's
     seed-ordered flow map (device tensors, reused by the next interval unless
-    copied).  With ``copy=True`` every grid is copied into a two-slot device
-    ring owned by the driver, so the simulation may overwrite its own buffer
-    right after the call; otherwise the caller must keep each grid unchanged
-    until the next cycle has been enqueued.
+    copied).  With ``copy=True`` every grid is copied into a device ring owned
+    by the driver, so the simulation may overwrite its own buffer right after
+    the call; otherwise the caller must keep each grid unchanged until the next
+    cycle has been enqueued.
+
+    ``overlap=True`` (needs ``copy=True``) runs the driver on two streams of
+    its own: the copy of each incoming grid on an ingest stream into a
+    three-slot ring, the advection on a compute stream.  Events order them:
+    the ingest copy waits for the simulation's stream to reach the call and
+    for the last step that read the slot it overwrites; the step waits for
+    the copy of its new grid; the simulation's stream waits only for the copy
+    (so it may overwrite its buffer), never for the advection, which therefore
+    overlaps the simulation's next cycle and the next copy.
     """
 
     def __init__(self, ctx: Context, interval: int, stride: int, mode: str = "linear", copy: bool = False,
-                 on_flowmap: Optional[Callable] = None, timing: bool = True):
+                 on_flowmap: Optional[Callable] = None, timing: bool = True, overlap: bool = False):
         if interval < 1:
             raise ValueError("interval must be >= 1")
+        if overlap and not copy:
+            raise ValueError("overlap needs copy=True (the driver must own the grids it reads later)")
         self.ctx = ctx
         self.interval = int(interval)
         self.stride = int(stride)
         self.mode = mode
         self.copy = copy
+        self.overlap = overlap
         self.on_flowmap = on_flowmap
         self.timing = timing
         self._prev = None
         self._prev_t = None
+        self._prev_slot = None
         self._ring: List[torch.Tensor] = []
         self._slot = 0
         self.steps_in_interval = 0
@@ -52,45 +65,79 @@ class InSituDriver:
         self._t0 = None
         self._events = []          # (start, end) per advection cycle
         self._out = None
+        if overlap:
+            self._compute = torch.cuda.Stream()   # default priority
+            self._ingest = torch.cuda.Stream()
+            self._read_done: List[Optional[torch.cuda.Event]] = [None, None, None]
+        else:
+            self._compute = None
 
-    def _own(self, grid: torch.Tensor) -> torch.Tensor:
+    def _own(self, grid: torch.Tensor):
         if not self.copy:
-            return grid
+            return grid, None
+        nslot = 3 if self.overlap else 2
         if not self._ring:
-            self._ring = [torch.empty_like(grid), torch.empty_like(grid)]
-        dst = self._ring[self._slot]
-        self._slot ^= 1
-        dst.copy_(grid)
-        return dst
+            self._ring = [torch.empty_like(grid) for _ in range(nslot)]
+        k = self._slot
+        self._slot = (k + 1) % nslot
+        dst = self._ring[k]
+        if not self.overlap:
+            dst.copy_(grid)
+            return dst, k
+        sim = torch.cuda.current_stream()
+        self._ingest.wait_stream(sim)                 # the grid is complete once the simulation gets here
+        if self._read_done[k] is not None:
+            self._ingest.wait_event(self._read_done[k])  # the step that last read this slot is done
+        with torch.cuda.stream(self._ingest):
+            dst.copy_(grid)
+        copied = torch.cuda.Event()
+        copied.record(self._ingest)
+        sim.wait_event(copied)                        # the simulation may overwrite its buffer after this
+        self._compute.wait_event(copied)              # the next step reads the copy
+        grid.record_stream(self._ingest)
+        return dst, k
 
     def _start_interval(self, t):
-        self.ctx.seed(self.stride)
+        self.ctx.seed(self.stride, stream=self._compute)
         self.steps_in_interval = 0
         self._t0 = t
 
     def cycle(self, grid: torch.Tensor, t: float):
         """Consume the grid of the next cycle at time ``t``."""
-        g = self._own(grid)
+        g, k = self._own(grid)
         if self._prev is None:
             self._start_interval(t)
         else:
+            cs = self._compute or torch.cuda.current_stream()
             if self.timing:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-            self.ctx.advect([self._prev, g], [self._prev_t, t], mode=self.mode)
+                e0.record(cs)
+            self.ctx.advect([self._prev, g], [self._prev_t, t], mode=self.mode, stream=self._compute)
             if self.timing:
-                e1.record()
+                e1.record(cs)
                 self._events.append((e0, e1))
+            if self.overlap:
+                done = torch.cuda.Event()
+                done.record(cs)
+                self._read_done[self._prev_slot] = done
+                self._read_done[k] = done
             self.steps_in_interval += 1
             if self.steps_in_interval == self.interval:
                 # write cycle: flow map of the finished interval, then reseed
-                self._out = self.ctx.flowmap(out=self._out)
+                self._out = self.ctx.flowmap(out=self._out, stream=self._compute)
                 if self.on_flowmap is not None:
+                    if self._compute is not None:
+                        torch.cuda.current_stream().wait_stream(self._compute)
                     self.on_flowmap(self.intervals_done, self._out, self._t0, t)
                 self.intervals_done += 1
                 self._start_interval(t)
-        self._prev, self._prev_t = g, t
+        self._prev, self._prev_t, self._prev_slot = g, t, k
+
+    def synchronize(self):
+        """Make the caller's current stream wait for everything the driver enqueued."""
+        if self._compute is not None:
+            torch.cuda.current_stream().wait_stream(self._compute)
 
     def mean_cycle_ms(self) -> float:
         """Average time per non-write cycle (advection + particle management)."""
