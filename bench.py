@@ -213,6 +213,70 @@ def insitu_overlap(log, n=128, modes=32):
     return out
 
 
+UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def precision_statement(log, threads):
+    """End-position error of the GPU path against the FP64 oracle on the FP64
+    field, per storage type, for the turbulence blocks (the 256^3 precision
+    workload in f32/f16/bf16, the 512^3 scale workload in f16 through a
+    two-slot ring), on a fixed seed subset; with the first-order bound
+    ||J|| N h max|V| (u_storage + 2^-21) per seed (J from the oracle's tangent,
+    u the storage's unit roundoff, 2^-21 the FP32 sampling arithmetic)."""
+    import torch
+    import oracle
+    from bto_inputs import _turb
+    from bto_inputs.workloads import WORKLOADS
+    from paper_2004_02003_amd import Context
+
+    out = {}
+    for name, every in (("turb_256", 509), ("turb_512", 32771)):  # steps coprime with the lattice rows
+        wl = WORKLOADS[name]
+        s = wl.make_field()
+        gen = _turb.DeviceTurbulence(s.lazy)
+        N = wl.n_steps
+        ids = np.arange(0, wl.n_seeds, every)
+        seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
+        t0 = time.perf_counter()
+        o = oracle.flowmap(oracle.Field.lazy_turbulence(s, "f64"), s.times, seeds, N, jac=True, nthreads=threads)
+        log(f"precision {name}: FP64 oracle on {len(ids)} seeds in {time.perf_counter() - t0:.1f} s")
+        nJ = np.linalg.norm(o["jac"], axis=(1, 2), ord=2)
+        shape = (wl.n[2], wl.n[1], wl.n[0], 3)
+        res = {}
+        for dt in wl.dtypes:
+            tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dt]
+            vmax = 0.0
+            with Context(wl.n, wl.n_seeds) as ctx:
+                ctx.set_tuning(**{k: v for k, v in LAUNCH_SHAPE.get(name, {}).items()})
+                ctx.seed(wl.stride)
+                slots = [torch.empty(shape, dtype=tdt, device="cuda") for _ in range(2)]
+                gen.fill(0, dt, slots[0])
+                for c in range(N):
+                    gen.fill(c + 1, dt, slots[(c + 1) % 2])
+                    if c % 10 == 0:
+                        vmax = max(vmax, float(slots[(c + 1) % 2].float().abs().max()))
+                    ctx.advect([slots[c % 2], slots[(c + 1) % 2]], s.times[c:c + 2])
+                fm = ctx.flowmap()
+                torch.cuda.synchronize()
+                end = fm["end"].cpu().numpy()[ids]
+                flag = fm["flag"].cpu().numpy()[ids]
+                del slots
+            torch.cuda.empty_cache()
+            both = (flag == 0) & (o["flag"] == 0)
+            err = np.linalg.norm(end[both] - o["end"][both], axis=1)
+            bound = nJ[both] * N * wl.dt * vmax * np.sqrt(3.0) * (UNIT_ROUNDOFF[dt] + 2.0 ** -21)
+            safe = o["margin"] >= 1e-6
+            res[dt] = {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
+                       "n": int(both.sum()), "within_first_order_bound_pct": round(100.0 * float((err <= bound).mean()), 2),
+                       "bound_median": float(np.median(bound)),
+                       "flag_disagree": int((flag != o["flag"]).sum()),
+                       "flag_disagree_outside_margin": int(((flag != o["flag"]) & safe).sum())}
+            log(f"precision {name} {dt}: {res[dt]}")
+        out[name] = {"seeds": f"every {every}th of {wl.n_seeds}", "steps": N, "cells": "end-position L2 error, cells",
+                     **res}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -444,6 +508,18 @@ def main(argv=None):
                                   "sample": f"{'all' if len(ids) == P else f'every {ids[1] - ids[0]}th'} seed(s) of "
                                             f"{wl.name} ({len(ids)} seeds x {N} steps) x {reps} repeats, {ps} "
                                             f"particle-steps in {tc:.1f} s, FP64, OpenMP"}
+        # the same oracle on one thread, on every 16th seed of the same sample
+        ids1 = ids[::16]
+        t1 = time.perf_counter()
+        o1 = oracle.flowmap(F, times, seeds[::16], N, nthreads=1)
+        t1 = time.perf_counter() - t1
+        ps1 = int(np.where(o1["flag"] == 0, N, o1["exit"] + 1).sum())
+        result["cpu_baseline_1thread"] = {"value": round(ps1 / t1, 1), "unit": "particle-RK4-steps/s", "cores": 1,
+                                          "kind": "oracle",
+                                          "sample": f"{len(ids1)} seeds x {N} steps, {ps1} particle-steps in "
+                                                    f"{t1:.1f} s, FP64"}
+        if not args.no_variants and wl.name == "abc_128":
+            result["precision_turbulence"] = precision_statement(log, threads)
 
     if args.copy_probe:
         x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
