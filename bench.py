@@ -71,10 +71,12 @@ def algorithmic_bytes(per_launch, dt: str, stride: int):
 # Per-cycle time of the paper's own metric (Section 4.2: mean time per
 # non-write cycle of advection + particle management) on the paper's per-rank
 # ABC shape: a 64^3 block of a 256^3 domain (64 ranks), one period in 1000
-# steps, interval 50, reductions 1:1 and 1:8.  Context only: the paper's
-# times (Table 2) are V100 times inside Ascent/VTK-h, a different machine
-# and framework.
-PAPER_TABLE2_MS = {(50, 1): 6.6, (50, 2): 3.3}
+# steps, intervals 25/50/100, reductions 1:1, 1:8, 1:27.  Context only: the
+# paper's times (ABC table, Lagrangian-BTO seconds per step) are V100 times
+# inside Ascent/VTK-h, a different machine and framework.
+PAPER_ABC_TABLE_MS = {(25, 1): 5.9, (50, 1): 6.6, (100, 1): 6.7,
+                      (25, 2): 2.6, (50, 2): 3.3, (100, 2): 2.6,
+                      (25, 3): 2.4, (50, 3): 2.9, (100, 3): 2.7}
 
 
 def paper_context(log):
@@ -83,40 +85,31 @@ def paper_context(log):
     from bto_inputs import fields
     from paper_2004_02003_amd import Context, InSituDriver, grid_to_device
 
-    n, interval, n_int = 64, 50, 4
-    s = fields.abc_noise(n, interval * n_int + 1, 2 * math.pi / 1000, sigma=0.0, global_n=256,
-                         offset=(64, 64, 64))
+    n, total = 64, 200
+    s = fields.abc_noise(n, total + 1, 2 * math.pi / 1000, sigma=0.0, global_n=256, offset=(64, 64, 64))
     dev = [grid_to_device(g, "f32") for g in s.grids("f32")]
     out = {}
-    for stride in (1, 2):
-        term = []
+    for interval in (25, 50, 100):
+        for stride in (1, 2, 3):
+            term = []
 
-        def keep(idx, fm, t0, t1, _term=term):
-            _term.append(float((fm["flag"] != 0).float().mean()))
+            def keep(idx, fm, t0, t1, _term=term):
+                _term.append(float((fm["flag"] != 0).float().mean()))
 
-        with Context((n, n, n), n ** 3) as ctx:
-            drv = InSituDriver(ctx, interval=interval, stride=stride, on_flowmap=keep)
-            for c in range(len(dev)):
-                drv.cycle(dev[c], float(s.times[c]))
-            torch.cuda.synchronize()
-            ms = drv.mean_cycle_ms()
-        key = f"abc_64_block_1to{stride ** 3}_interval{interval}"
-        out[key] = {"ms_per_cycle": round(ms, 4),
-                    "discarded_pct": round(100 * sum(term) / len(term), 2),
-                    "paper_v100_ms_per_cycle": PAPER_TABLE2_MS[(interval, stride)]}
-        out[key]["particles"] = ((n - 1 - (stride - 1) // 2) // stride + 1) ** 3
-        log(f"paper context {key}: {ms:.4f} ms per cycle")
+            with Context((n, n, n), n ** 3) as ctx:
+                drv = InSituDriver(ctx, interval=interval, stride=stride, on_flowmap=keep)
+                for c in range(len(dev)):
+                    drv.cycle(dev[c], float(s.times[c]))
+                torch.cuda.synchronize()
+                ms = drv.mean_cycle_ms()
+                particles = ctx.n_seeds
+            key = f"abc_64_block_1to{stride ** 3}_interval{interval}"
+            out[key] = {"ms_per_cycle": round(ms, 4),
+                        "discarded_pct": round(100 * sum(term) / len(term), 2),
+                        "paper_v100_ms_per_cycle": PAPER_ABC_TABLE_MS[(interval, stride)],
+                        "particles": particles, "intervals": len(term)}
+            log(f"paper context {key}: {ms:.4f} ms per cycle")
     return out
-
-
-# Launch shape per workload (results do not depend on it).  The coherent ABC
-# block runs best as seeded; the turbulent blocks mix their particles, so a
-# periodic re-sort restores cache locality, and for FP32 grids two lanes per
-# particle halve the cache lines a row load touches.
-LAUNCH_SHAPE = {
-    "turb_256": dict(rebin_every=5, lanes_per_particle=2),
-    "turb_512": dict(rebin_every=10, lanes_per_particle=2),
-}
 
 
 def posthoc_accuracy(log):
