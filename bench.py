@@ -270,6 +270,63 @@ def precision_statement(log, threads):
     return out
 
 
+def differentiation(log):
+    """The differentiation workload: 32^3 seeds (stride 4) on the 128^3 ABC
+    field, 100 steps, checkpoints every 10.  Times (HIP events, median of 5)
+    of the adjoint for the seeded-weight loss (seed gradients, and seed plus
+    grid gradients), and of the flow-map Jacobian with FTLE for every seed.
+    Throughput counts forward particle-steps of the interval per second of
+    the whole backward call (checkpointed forward + recompute + reverse)."""
+    import torch
+    from bto_inputs.workloads import WORKLOADS, loss_weights
+    from paper_2004_02003_amd import Context, grid_to_device, jacobian_ftle
+
+    wl = WORKLOADS["abc_128_adjoint"]
+    s = wl.make_field()
+    dev = [grid_to_device(g, "f32") for g in s.grids("f32")]
+    k = wl.extra["ckpt_every"]
+    out = {"workload": f"{wl.name}: {wl.n_seeds} seeds, {wl.n_steps} steps, checkpoint every {k}"}
+    with Context(wl.n, wl.n_seeds) as ctx:
+        ctx.seed(wl.stride)
+        ctx.advect(dev, s.times)
+        psteps = ctx.stats()["particle_steps"]
+        w = torch.as_tensor(loss_weights(wl.n_seeds, wl.extra["weight_seed"]), dtype=torch.float32,
+                            device="cuda").contiguous()
+        gg = [torch.zeros(g.shape, dtype=torch.float32, device="cuda") for g in dev]
+        seeds = ctx.flowmap()["seed"].clone()
+
+        def timed(fn, reps=5):
+            ts = []
+            for _ in range(reps + 1):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return float(np.median(ts[1:]))
+
+        def seed_grad():
+            ctx.seed(wl.stride)
+            ctx.adjoint(dev, s.times, w, ckpt_every=k)
+
+        def seed_and_grid_grad():
+            ctx.seed(wl.stride)
+            ctx.adjoint(dev, s.times, w, grad_grids=gg, ckpt_every=k)
+
+        def jac():
+            jacobian_ftle(ctx, seeds, dev, s.times, ckpt_every=k)
+
+        for name, fn in (("seed_gradient", seed_grad), ("seed_and_grid_gradient", seed_and_grid_grad),
+                         ("jacobian_ftle", jac)):
+            ms = timed(fn)
+            out[name] = {"ms": round(ms, 4), "forward_particle_steps_per_s": round(psteps / (ms * 1e-3), 1)}
+            log(f"differentiation {name}: {ms:.3f} ms")
+    del dev, gg
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -477,6 +534,7 @@ def main(argv=None):
         result["paper_context"] = paper_context(log)
         result["posthoc_accuracy"] = posthoc_accuracy(log)
         result["insitu_overlap"] = [insitu_overlap(log, 128, 32), insitu_overlap(log, 256, 64)]
+        result["differentiation"] = differentiation(log)
 
     if not args.no_cpu_baseline:
         ids = np.arange(0, P, 1 if not turb else 1024)

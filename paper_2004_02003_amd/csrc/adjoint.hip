@@ -80,10 +80,47 @@ __device__ __forceinline__ void gT(const float G[3][3], const float v[3], float 
     for (int d = 0; d < 3; ++d) out[d] = G[0][d] * v[0] + G[1][d] * v[1] + G[2][d] * v[2];
 }
 
-// scatter coef * w_corner(f) * inv_sp_r * lam_r into grid `gf` at the cell
-__device__ __forceinline__ void scatter_cell(const Geom& g, float* gf, uint32_t base, const float f[3], float coef,
-                                             const float lam[3]) {
-    if (!gf) return;
+
+// Grid-gradient accumulator: the 8 corner gradients of one cell of one grid
+// level, summed in registers while consecutive stage contributions hit the
+// same cell and level, and added to the grid with atomics only when the cell
+// or level changes (and at the end of each checkpoint segment).  In the
+// reverse sweep a level receives its contributions from two consecutive
+// steps (level n from step n's first three stages and from step n-1's last
+// three), so a particle that stays in its cell flushes once per level.
+struct GradAcc {
+    uint32_t base;
+    int level;
+    float v[8][3];
+};
+
+__device__ __forceinline__ void acc_flush(const Geom& g, float* const* gf, GradAcc& A) {
+    if (A.base == NO_CELL) return;
+    float* grid = gf[A.level];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                float* p = grid + 3 * ((uint64_t)A.base + (uint64_t)q + (uint64_t)g.sy * b + (uint64_t)g.sz * c);
+                const int k = q + 2 * b + 4 * c;
+                unsafeAtomicAdd(p + 0, A.v[k][0]);
+                unsafeAtomicAdd(p + 1, A.v[k][1]);
+                unsafeAtomicAdd(p + 2, A.v[k][2]);
+            }
+    A.base = NO_CELL;
+}
+
+__device__ __forceinline__ void acc_add(const Geom& g, float* const* gf, GradAcc& A, int level, uint32_t base,
+                                        const float f[3], float coef, const float lam[3]) {
+    if (A.base != base || A.level != level) {
+        acc_flush(g, gf, A);
+        A.base = base;
+        A.level = level;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) A.v[k][0] = A.v[k][1] = A.v[k][2] = 0.f;
+    }
     const float wx[2] = {1.f - f[0], f[0]}, wy[2] = {1.f - f[1], f[1]}, wz[2] = {1.f - f[2], f[2]};
     const float l[3] = {(float)g.inv_sp[0] * lam[0] * coef, (float)g.inv_sp[1] * lam[1] * coef,
                         (float)g.inv_sp[2] * lam[2] * coef};
@@ -92,12 +129,12 @@ __device__ __forceinline__ void scatter_cell(const Geom& g, float* gf, uint32_t 
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const float w = wx[a] * wy[b] * wz[c];
-                float* p = gf + 3 * ((uint64_t)base + (uint64_t)a + (uint64_t)g.sy * b + (uint64_t)g.sz * c);
-                unsafeAtomicAdd(p + 0, w * l[0]);
-                unsafeAtomicAdd(p + 1, w * l[1]);
-                unsafeAtomicAdd(p + 2, w * l[2]);
+            for (int q = 0; q < 2; ++q) {
+                const float w = wx[q] * wy[b] * wz[c];
+                const int k = q + 2 * b + 4 * c;
+                A.v[k][0] = fmaf(w, l[0], A.v[k][0]);
+                A.v[k][1] = fmaf(w, l[1], A.v[k][1]);
+                A.v[k][2] = fmaf(w, l[2], A.v[k][2]);
             }
 }
 
@@ -131,6 +168,9 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
         for (int d = 0; d < 3; ++d)
             lam[c][d] = status == S_VALID ? a.cot[(p * NCOT + c) * 3 + d] * (float)a.sp[d] : 0.f;
 
+    GradAcc acc;
+    acc.base = NO_CELL;
+    acc.level = -1;
     if (status == S_VALID) {
         for (int sg = nseg - 1; sg >= 0; --sg) {
             const int n0 = sg * K;
@@ -167,24 +207,24 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
                     for (int d = 0; d < 3; ++d) lk[0][d] = (h / 6.f) * lam[c][d] + (0.5f * h) * ly[1][d];
                     gT(rec.G[0], lk[0], ly[0]);
                     if (c == 0 && a.grad_f) {
-                        float* g0 = a.grad_f[n];
-                        float* g1 = a.grad_f[n + 1];
                         if (MODE == MODE_FROZEN) {
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) scatter_cell(a.g, g0, rec.base[s], rec.f[s], 1.f, lk[s]);
+                            for (int s = 0; s < 4; ++s) acc_add(a.g, a.grad_f, acc, n, rec.base[s], rec.f[s], 1.f, lk[s]);
                         } else {
-                            scatter_cell(a.g, g0, rec.base[0], rec.f[0], 1.f, lk[0]);
-                            scatter_cell(a.g, g0, rec.base[1], rec.f[1], 0.5f, lk[1]);
-                            scatter_cell(a.g, g1, rec.base[1], rec.f[1], 0.5f, lk[1]);
-                            scatter_cell(a.g, g0, rec.base[2], rec.f[2], 0.5f, lk[2]);
-                            scatter_cell(a.g, g1, rec.base[2], rec.f[2], 0.5f, lk[2]);
-                            scatter_cell(a.g, g1, rec.base[3], rec.f[3], 1.f, lk[3]);
+                            // level n+1 first (it already holds step n+1's share), then level n
+                            acc_add(a.g, a.grad_f, acc, n + 1, rec.base[1], rec.f[1], 0.5f, lk[1]);
+                            acc_add(a.g, a.grad_f, acc, n + 1, rec.base[2], rec.f[2], 0.5f, lk[2]);
+                            acc_add(a.g, a.grad_f, acc, n + 1, rec.base[3], rec.f[3], 1.f, lk[3]);
+                            acc_add(a.g, a.grad_f, acc, n, rec.base[0], rec.f[0], 1.f, lk[0]);
+                            acc_add(a.g, a.grad_f, acc, n, rec.base[1], rec.f[1], 0.5f, lk[1]);
+                            acc_add(a.g, a.grad_f, acc, n, rec.base[2], rec.f[2], 0.5f, lk[2]);
                         }
                     }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) lam[c][d] += ly[0][d] + ly[1][d] + ly[2][d] + ly[3][d];
                 }
             }
+            if (a.grad_f) acc_flush(a.g, a.grad_f, acc);  // keep the accumulator out of the next recompute
         }
     }
 #pragma unroll
