@@ -112,6 +112,16 @@ def paper_context(log):
     return out
 
 
+# Launch shape per workload (results do not depend on it).  The coherent ABC
+# block runs best as seeded; the turbulent blocks mix their particles, so a
+# periodic re-sort restores cache locality, and for FP32 grids two lanes per
+# particle halve the cache lines a row load touches.
+LAUNCH_SHAPE = {
+    "turb_256": dict(rebin_every=5, lanes_per_particle=2),
+    "turb_512": dict(rebin_every=10, lanes_per_particle=2),
+}
+
+
 def posthoc_accuracy(log):
     """The paper's accuracy experiment (Section 4) at node scale on one GPU:
     a 128^3-cell ABC domain cut into 2 x 2 x 2 blocks of 64^3 cells (the

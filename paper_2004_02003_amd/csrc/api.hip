@@ -28,6 +28,7 @@ struct bto_ctx {
     int rebin_every = 0;          // re-sort live particles every this many steps (BTO_REBIN_EVERY; 0 = never)
     int lanes_per_particle = 1;   // FP32 grids: 1 or 2 lanes per particle (BTO_LANES_PER_PARTICLE)
     int morton_seed = 0;          // Morton brick order at seeding when possible (BTO_MORTON_SEED)
+    int octant_seed = 1;          // octant-major seeding, one lattice octant per XCD segment (BTO_OCTANT_SEED=0: slabs)
     int brick[3] = {64, 1, 1};    // lattice points per seeding brick (BTO_BRICK="bx,by,bz", product 64)
     int steps_since_rebin = 0;
     uint32_t* rebin_buf = nullptr;  // 4 x cap keys/values
@@ -132,6 +133,7 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     if (const char* e = std::getenv("BTO_BLOCKS_PER_CU")) c->blocks_per_cu_cap = std::atoi(e);
     if (const char* e = std::getenv("BTO_REBIN_EVERY")) c->rebin_every = std::atoi(e) > 0 ? std::atoi(e) : 0;
     if (const char* e = std::getenv("BTO_MORTON_SEED")) c->morton_seed = std::atoi(e) != 0;
+    if (const char* e = std::getenv("BTO_OCTANT_SEED")) c->octant_seed = std::atoi(e) != 0;
     if (const char* e = std::getenv("BTO_LANES_PER_PARTICLE")) c->lanes_per_particle = std::atoi(e) == 2 ? 2 : 1;
     if (const char* e = std::getenv("BTO_BRICK")) {
         int b0 = 0, b1 = 0, b2 = 0;
@@ -281,6 +283,23 @@ int bto_seed(bto_ctx* c, int32_t stride, const double* offset3, int64_t* n_seeds
         a.morton = (a.m[0] == a.m[1] && a.m[1] == a.m[2] && a.m[0] % 4 == 0 && pow2 && c->morton_seed) ? 1 : 0;
     }
     set_segments(c, P);
+    if (c->octant_seed && !a.morton) {
+        // one lattice octant per segment (each XCD keeps a compact octant of the block)
+        a.octant = 1;
+        int64_t size[NSEG];
+        for (int d = 0; d < 3; ++d) a.half[d] = (a.m[d] + 1) / 2;
+        for (int o = 0; o < NSEG; ++o) {
+            size[o] = 1;
+            for (int d = 0; d < 3; ++d) size[o] *= ((o >> d) & 1) ? a.m[d] - a.half[d] : a.half[d];
+        }
+        int64_t acc = 0;
+        for (int o = 0; o < NSEG; ++o) {
+            a.oct_base[o] = acc;
+            c->segs.base[o] = acc;
+            c->seg_cap[o] = size[o];
+            acc += size[o];
+        }
+    }
     a.segs = c->segs;
     a.pos = c->pos[0];
     a.id = c->id[0];

@@ -41,6 +41,9 @@ struct SeedLatticeArgs {
     double off[3];       // lattice offset (cells)
     int32_t stride;
     int32_t morton;      // bricks in Morton order (power-of-two cube of bricks)
+    int32_t octant;      // octant-major order: segment x = lattice octant x, x-fastest inside
+    int32_t half[3];     // octant split per axis: indices < half[d] are the low half
+    int64_t oct_base[NSEG];  // first slot of each octant
     int32_t brick[3];    // lattice points per brick and axis (product 64)
     int64_t P;
     Segs segs;

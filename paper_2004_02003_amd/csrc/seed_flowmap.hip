@@ -8,13 +8,16 @@ namespace bto {
 // Seeding.
 // ---------------------------------------------------------------------------
 
-// Lattice points are stored brick-major: bricks of B0 x B1 x B2 = 64 lattice
-// points (one wavefront) in x-fastest brick order, x-fastest inside a brick.
-// The default brick, 64 x 1 x 1, is the natural x-fastest lattice order: a
-// wavefront's lanes lie along one grid row, so each of a cell's four row loads
-// covers one long contiguous run of the grid (measured best for the gather).
-// Bricks on the high faces may be partial; slot(id) is the closed-form prefix
-// count.
+// Slot order of the lattice.  Default: octant-major -- the lattice is split
+// in two per axis and each octant fills one XCD segment, in natural x-fastest
+// order inside it (a wavefront's lanes lie along grid rows, so each of a
+// cell's four row loads covers long contiguous runs of the grid, and each
+// XCD keeps a compact octant of the block).  Alternatives for experiments:
+// brick-major -- bricks of B0 x B1 x B2 = 64 lattice points (one wavefront)
+// in x-fastest brick order, x-fastest inside a brick (64 x 1 x 1 is the plain
+// natural order, the segments then being z-slabs); bricks on the high faces
+// may be partial and slot(id) is the closed-form prefix count -- and Morton
+// order of 4 x 4 x 4 bricks.
 __device__ __forceinline__ int64_t brick_slot(const int32_t m[3], const int32_t B[3], int a, int b, int c) {
     const int bx = a / B[0], by = b / B[1], bz = c / B[2];
     const int lx = a % B[0], ly = b % B[1], lz = c % B[2];
@@ -41,9 +44,20 @@ __global__ __launch_bounds__(BLOCK) void seed_lattice_kernel(const SeedLatticeAr
         const int ic = (int)(t / ((int64_t)a.m[0] * a.m[1]));
         const double x[3] = {a.off[0] + (double)a.stride * ia, a.off[1] + (double)a.stride * ib,
                              a.off[2] + (double)a.stride * ic};
-        const int64_t slot = a.morton ? (int64_t)(spread3b(ia >> 2) | (spread3b(ib >> 2) << 1) | (spread3b(ic >> 2) << 2)) *
-                                                64 + ((ia & 3) + 4 * ((ib & 3) + 4 * (ic & 3)))
-                                      : brick_slot(a.m, a.brick, ia, ib, ic);
+        int64_t slot;
+        if (a.octant) {
+            // octant-major: octant o = (x high) + 2 (y high) + 4 (z high), x-fastest inside it
+            const int hx = ia >= a.half[0], hy = ib >= a.half[1], hz = ic >= a.half[2];
+            const int lx = ia - hx * a.half[0], ly = ib - hy * a.half[1], lz = ic - hz * a.half[2];
+            const int sx = hx ? a.m[0] - a.half[0] : a.half[0];
+            const int sy = hy ? a.m[1] - a.half[1] : a.half[1];
+            slot = a.oct_base[hx + 2 * hy + 4 * hz] + lx + (int64_t)sx * (ly + (int64_t)sy * lz);
+        } else if (a.morton) {
+            slot = (int64_t)(spread3b(ia >> 2) | (spread3b(ib >> 2) << 1) | (spread3b(ic >> 2) << 2)) * 64 +
+                   ((ia & 3) + 4 * ((ib & 3) + 4 * (ic & 3)));
+        } else {
+            slot = brick_slot(a.m, a.brick, ia, ib, ic);
+        }
         a.pos[slot] = pack(x);
         a.id[slot] = (uint32_t)t;
 #pragma unroll

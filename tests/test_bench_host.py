@@ -1,0 +1,54 @@
+"""Host-side logic of bench.py (no GPU): the launch plan mirrors the library's
+balanced split, the algorithmic-bytes model is the stated per-unit figure,
+the per-workload launch shapes name real workloads, and the entry point
+refuses more than one GPU before touching a device."""
+
+import importlib.util
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_launch_plan_matches_the_library_split(bench):
+    assert bench.launch_plan(100, 32, 0) == [25, 25, 25, 25]
+    assert bench.launch_plan(100, 32, 5) == [5] * 20          # re-sorting caps the launch length
+    assert bench.launch_plan(7, 32, 0) == [7]
+    assert bench.launch_plan(50, 128, 0) == [50]
+    plan = bench.launch_plan(201, 32, 0)
+    assert sum(plan) == 201 and max(plan) - min(plan) <= 1 and max(plan) <= 32
+
+
+def test_algorithmic_bytes_per_unit_figure(bench):
+    # one level over 8 points per particle-step (96 B f32, 48 B f16) plus, per launch,
+    # the first level and 40 B of state per live particle
+    assert bench.algorithmic_bytes([(1000, 25000)], "f32", 2) == 96 * (25000 + 1000) + 40 * 1000
+    assert bench.algorithmic_bytes([(10, 100), (8, 80)], "f16", 2) == 48 * 110 + 400 + 48 * 88 + 320
+
+
+def test_launch_shapes_and_tables_are_consistent(bench):
+    from bto_inputs.workloads import WORKLOADS
+
+    assert set(bench.LAUNCH_SHAPE) <= set(WORKLOADS)
+    for shape in bench.LAUNCH_SHAPE.values():
+        assert set(shape) <= {"steps_per_launch", "rebin_every", "blocks_per_cu", "lanes_per_particle"}
+    assert set(bench.PAPER_ABC_TABLE_MS) == {(i, s) for i in (25, 50, 100) for s in (1, 2, 3)}
+    assert set(bench.UNIT_ROUNDOFF) == {"f32", "f16", "bf16"}
+    for fn in ("paper_context", "posthoc_accuracy", "insitu_overlap", "precision_statement", "differentiation",
+               "kernel_hash", "main"):
+        assert callable(getattr(bench, fn)), fn
+
+
+def test_more_than_one_gpu_is_refused(bench):
+    with pytest.raises(SystemExit) as e:
+        bench.main(["--gpus", "2"])
+    assert e.value.code == 2
