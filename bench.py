@@ -579,8 +579,14 @@ def main(argv=None):
             reps += 1
             if tc > 30.0:
                 break
+        cpu_model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu_model)
+        except OSError:
+            pass
         result["cpu_baseline"] = {"value": round(ps / tc, 1), "unit": "particle-RK4-steps/s", "cores": threads,
-                                  "kind": "oracle",
+                                  "kind": "oracle", "cpu": cpu_model, "nproc": os.cpu_count(),
                                   "sample": f"{'all' if len(ids) == P else f'every {ids[1] - ids[0]}th'} seed(s) of "
                                             f"{wl.name} ({len(ids)} seeds x {N} steps) x {reps} repeats, {ps} "
                                             f"particle-steps in {tc:.1f} s, FP64, OpenMP"}
