@@ -7,6 +7,7 @@ from the oracle run on the very same stored grid values.
 """
 
 import math
+import os
 import sys
 
 import numpy as np
@@ -430,6 +431,22 @@ def test_seed_orders_give_identical_flow_maps(n):
             assert np.array_equal(runs[name][k], runs["octant"][k]), (name, k)
         assert np.array_equal(runs[name]["face"], runs["octant"]["face"], equal_nan=True)
         assert runs[name]["stats"] == runs["octant"]["stats"]
+
+
+def test_plain_c_consumer_of_the_c_abi():
+    """The C program paper_2004_02003_amd/c_abi_demo.c (no Python, no PyTorch:
+    HIP runtime for memory, libbto.so for everything else) checks a uniform
+    flow interval with non-uniform steps against the closed form, including
+    exit points and an out-of-order call; run here as a child process."""
+    import subprocess
+
+    from paper_2004_02003_amd import build as hip_build
+
+    _say("plain C consumer of the C-ABI")
+    assert os.path.exists(hip_build.DEMO), "build() compiles the C demo next to libbto.so"
+    r = subprocess.run([hip_build.DEMO], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.startswith("c-abi demo ok"), r.stdout
 
 
 def test_error_paths_and_tuning_through_the_c_abi():
