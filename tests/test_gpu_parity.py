@@ -499,3 +499,38 @@ def test_error_paths_and_tuning_through_the_c_abi():
         assert e.value.code == _lib.BTO_EINVAL
     with pytest.raises(BTOError):
         Context((1, 4, 4), 10)
+
+
+def test_randomized_small_blocks_against_the_oracle():
+    """Seeded random small cases: block sizes down to 2 points per axis, seeds
+    anywhere (on faces, outside, near edges), 1 to 9 steps with random
+    non-uniform times, every launch shape and the exit-point variant; flags
+    and exit steps bit-exact outside the 1e-6 margin, positions within 1e-5."""
+    rng = np.random.default_rng(2024)
+    for case in range(24):
+        n = tuple(int(v) for v in rng.integers(2, 14, 3))
+        N = int(rng.integers(1, 10))
+        times = np.concatenate([[rng.uniform(-1, 1)], rng.uniform(0.05, 0.3, N)]).cumsum()
+        s = fields.abc_noise(n, N + 1, 0.1, sigma=0.05, seed=100 + case, global_n=int(rng.integers(6, 24)))
+        dt = ["f32", "f16", "bf16"][case % 3]
+        gr = s.grids(dt)
+        hi = np.array(n, dtype=float) - 1
+        P = int(rng.integers(1, 300))
+        seeds = rng.uniform(-0.5, 1.5, (P, 3)) * hi
+        k = rng.integers(0, P, P // 4)
+        ax = rng.integers(0, 3, len(k))
+        seeds[k, ax] = np.where(rng.random(len(k)) < 0.5, 0.0, hi[ax])  # seeds on faces
+        tuning = dict(steps_per_launch=int(rng.integers(1, 6)), rebin_every=int(rng.integers(0, 4)),
+                      lanes_per_particle=int(rng.integers(1, 3)))
+        mode = "frozen" if case % 5 == 4 else "linear"
+        chunks = None
+        if N >= 3 and case % 2:
+            cut = int(rng.integers(1, N))
+            chunks = [cut, N - cut]
+        _say(f"random case {case}: n={n} N={N} P={P} {dt} {mode} {tuning} chunks={chunks}")
+        g = run_gpu(n, _dev(gr, dt), times, seeds=seeds, mode=mode, chunks=chunks, tuning=tuning,
+                    record_exit=(case % 2 == 0))
+        o = oracle.flowmap(oracle.Field(n, gr, dtype=dt), times, seeds, N,
+                           mode=oracle.FROZEN if mode == "frozen" else oracle.LINEAR)
+        compare(g, o, label=f"random case {case}")
+        assert g["n_valid"] == int((g["flag"] == 0).sum())
