@@ -178,8 +178,9 @@ typedef struct {
 int bto_set_tuning(bto_ctx *ctx, const bto_tuning *t);
 int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
 
-/* Discrete adjoint of the interval (gradients for the north-star
- * differentiation workload; FTLE use of the flow map: Results section).
+/* Discrete adjoint of the interval: gradients of end positions with respect
+ * to seed positions (the flow-map Jacobian, hence FTLE -- the paper's FTLE
+ * use of flow maps, Results section) and to the velocity grids.
  * For the seeds of the current interval (bto_seed*), recompute the RK4
  * advection through d_fields / times (same meaning as bto_advect_interval,
  * all n_steps + 1 grids resident), storing each particle's position every
