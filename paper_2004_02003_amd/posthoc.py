@@ -93,10 +93,14 @@ def run_blocks(grids: Sequence[torch.Tensor], times, blocks: Tuple[int, int, int
 
     grids: N+1 domain grids (Nz, Ny, Nx, 3) on the device with N_d =
     blocks_d * cells_d + 1 points; every block's cell count must be a multiple
-    of ``stride`` so that the block lattices form one domain lattice.  Returns
+    of ``stride`` (>= 2) so that the block lattices tile the domain lattice.  Returns
     (end (P,3) f64, flag (P,) u8, lattice M) in domain-lattice order (x
     fastest), positions in domain coordinates (origin 0, the given spacing).
     """
+    if stride < 2:
+        # at stride 1 the lattice has seeds on the faces that neighbouring blocks share,
+        # so block lattices overlap instead of tiling the domain lattice
+        raise ValueError("run_blocks needs stride >= 2 (stride 1 seeds the shared block faces twice)")
     nz, ny, nx = (int(v) for v in grids[0].shape[:3])
     npts = (nx, ny, nz)
     cells = []
