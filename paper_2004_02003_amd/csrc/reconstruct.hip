@@ -140,17 +140,34 @@ __global__ __launch_bounds__(BLOCK) void err_partial_kernel(int64_t P, const dou
     if (threadIdx.x == 0) part[blockIdx.x] = ErrPart{s_sum[0], s_max[0], s_n[0], s_u[0]};
 }
 
-// Fixed-order sum of the partials (deterministic for a given grid).
-__global__ void err_final_kernel(int nparts, const ErrPart* part, ErrPart* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    ErrPart r{0.0, 0.0, 0ull, 0ull};
-    for (int i = 0; i < nparts; ++i) {
-        r.sum += part[i].sum;
-        r.max = fmax(r.max, part[i].max);
-        r.n += part[i].n;
-        r.uncovered += part[i].uncovered;
+// Fixed-order sum of the partials (deterministic for a given grid): each of
+// BLOCK threads sums a strided subset in order, then a fixed tree in LDS.
+__global__ __launch_bounds__(BLOCK) void err_final_kernel(int nparts, const ErrPart* part, ErrPart* out) {
+    double sum = 0.0, mx = 0.0;
+    unsigned long long n = 0, unc = 0;
+    for (int i = threadIdx.x; i < nparts; i += BLOCK) {
+        sum += part[i].sum;
+        mx = fmax(mx, part[i].max);
+        n += part[i].n;
+        unc += part[i].uncovered;
     }
-    *out = r;
+    __shared__ double s_sum[BLOCK], s_max[BLOCK];
+    __shared__ unsigned long long s_n[BLOCK], s_u[BLOCK];
+    s_sum[threadIdx.x] = sum;
+    s_max[threadIdx.x] = mx;
+    s_n[threadIdx.x] = n;
+    s_u[threadIdx.x] = unc;
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s_sum[threadIdx.x] += s_sum[threadIdx.x + o];
+            s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + o]);
+            s_n[threadIdx.x] += s_n[threadIdx.x + o];
+            s_u[threadIdx.x] += s_u[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = ErrPart{s_sum[0], s_max[0], s_n[0], s_u[0]};
 }
 
 // Copy a block's seed-ordered flow map (lattice mb, x fastest) into a larger
@@ -208,7 +225,7 @@ hipError_t launch_flowmap_error(int64_t P, const double* b, const uint8_t* bstat
     hipLaunchKernelGGL(err_partial_kernel, dim3(parts), dim3(BLOCK), 0, s, P, b, bstate, m, mflag, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(err_final_kernel, dim3(1), dim3(64), 0, s, parts, part, part + parts);
+    hipLaunchKernelGGL(err_final_kernel, dim3(1), dim3(BLOCK), 0, s, parts, part, part + parts);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     ErrPart r;

@@ -76,8 +76,24 @@ __global__ __launch_bounds__(BLOCK) void seed_explicit_kernel(const SeedExplicit
             x[d] = (w - a.origin[d]) * a.inv_sp[d];
         }
         const int seg = (int)((t * NSEG) / a.P);
-        if (inside(a.g, x)) {
-            const uint32_t k = atomicAdd(&a.count[seg], 1u);
+        const bool in = inside(a.g, x);
+        // slots in the segment: one atomic per wavefront and segment (a wavefront's
+        // seeds span one or two segments), ranks from the ballot
+        const int lane = threadIdx.x % WAVE;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        unsigned long long pending = __ballot(in);
+        uint32_t k = 0;
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int lseg = __shfl(seg, leader);
+            const unsigned long long same = __ballot(in && seg == lseg) & pending;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&a.count[lseg], (uint32_t)__popcll(same));
+            base = __shfl(base, leader);
+            if (in && seg == lseg) k = base + (uint32_t)__popcll(same & below);
+            pending &= ~same;
+        }
+        if (in) {
             a.pos[a.segs.base[seg] + k] = pack(x);
             a.id[a.segs.base[seg] + k] = (uint32_t)t;
             a.rec_meta[t] = META_LIVE;
