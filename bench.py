@@ -344,8 +344,13 @@ def differentiation(log):
         def jac():
             jacobian_ftle(ctx, seeds, dev, s.times, ckpt_every=k)
 
+        def seed_grad_every_step():
+            # a checkpoint at every step (N x P x 24 B) removes the recompute sweep
+            ctx.seed(wl.stride)
+            ctx.adjoint(dev, s.times, w, ckpt_every=1)
+
         for name, fn in (("seed_gradient", seed_grad), ("seed_and_grid_gradient", seed_and_grid_grad),
-                         ("jacobian_ftle", jac)):
+                         ("jacobian_ftle", jac), ("seed_gradient_checkpoint_every_step", seed_grad_every_step)):
             ms = timed(fn)
             out[name] = {"ms": round(ms, 4), "forward_particle_steps_per_s": round(psteps / (ms * 1e-3), 1)}
             log(f"differentiation {name}: {ms:.3f} ms")

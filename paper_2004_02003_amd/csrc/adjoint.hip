@@ -75,6 +75,19 @@ __device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const
     return S_VALID;
 }
 
+// Pointers read from a device array (the grid tables) are generic to the
+// compiler, which then emits flat memory instructions for every gather and
+// atomic through them; flat instructions also count against the scalar-load
+// counter, so their waits and those of scalar loads merge.  Every grid lives in
+// global memory: rebuilding the pointer in the global address space (through
+// its integer value, which no pass folds back into the generic pointer) lets
+// the compiler emit the global forms.
+template <class T>
+__device__ __forceinline__ T* in_global(T* p) {
+    using G = __attribute__((address_space(1))) T*;
+    return (T*)(G)(uintptr_t)p;
+}
+
 __device__ __forceinline__ void gT(const float G[3][3], const float v[3], float out[3]) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) out[d] = G[0][d] * v[0] + G[1][d] * v[1] + G[2][d] * v[2];
@@ -96,7 +109,7 @@ struct GradAcc {
 
 __device__ __forceinline__ void acc_flush(const Geom& g, float* const* gf, GradAcc& A) {
     if (A.base == NO_CELL) return;
-    float* grid = gf[A.level];
+    float* grid = in_global(gf[A.level]);
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -138,14 +151,24 @@ __device__ __forceinline__ void acc_add(const Geom& g, float* const* gf, GradAcc
             }
 }
 
+// One wavefront per workgroup: the adjoint holds about 280 registers per lane
+// (one wavefront per SIMD), so a seed set of a few tens of thousands fills
+// only a fraction of the SIMDs; single-wavefront workgroups spread those
+// wavefronts over every CU (and its L1 and texture pipeline) instead of
+// packing four of them onto each of the first P/256 CUs.
+constexpr int ADJ_BLOCK = WAVE;
+
 template <int DT, int MODE, int NCOT>
-__global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+__global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
     if (p >= a.P) return;
     const int N = a.N, K = a.k;
     const int nseg = (N + K - 1) / K;
-    double* ck = a.ckpt + (size_t)p * 3 * (nseg > 0 ? nseg : 1);
-    double* buf = a.buf + (size_t)p * 3 * K;
+    // checkpoints and recomputed step starts, slot-major ([slot][seed][xyz]), so a
+    // wavefront's 64 positions of one slot are one contiguous 1.5 KB run
+    const size_t P3 = (size_t)a.P * 3;
+    double* ck = a.ckpt + (size_t)p * 3;
+    double* buf = a.buf + (size_t)p * 3;
 
     Stepper<DT> st;
     stepper_init(st);
@@ -155,9 +178,9 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
     for (int n = 0; n < N && status == S_VALID; ++n) {
         if (n % K == 0) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) ck[3 * (n / K) + d] = st.x[d];
+            for (int d = 0; d < 3; ++d) ck[P3 * (size_t)(n / K) + d] = st.x[d];
         }
-        status = rk4_step_alt<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], n, st);
+        status = rk4_step_alt<DT, MODE>(a.g, in_global(a.f[n]), in_global(a.f[n + 1]), a.h[n], n, st);
     }
     if (a.status_out) a.status_out[p] = (uint8_t)status;
 
@@ -177,19 +200,19 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const AdjointArgs a) {
             const int n1 = (n0 + K < N) ? n0 + K : N;
             stepper_init(st);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) st.x[d] = ck[3 * sg + d];
+            for (int d = 0; d < 3; ++d) st.x[d] = ck[P3 * (size_t)sg + d];
             for (int n = n0; n < n1; ++n) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) buf[3 * (n - n0) + d] = st.x[d];
-                if (n + 1 < n1) rk4_step_alt<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], n - n0, st);
+                for (int d = 0; d < 3; ++d) buf[P3 * (size_t)(n - n0) + d] = st.x[d];
+                if (n + 1 < n1) rk4_step_alt<DT, MODE>(a.g, in_global(a.f[n]), in_global(a.f[n + 1]), a.h[n], n - n0, st);
             }
             for (int n = n1 - 1; n >= n0; --n) {
                 Stepper<DT> sr;
                 stepper_init(sr);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) sr.x[d] = buf[3 * (n - n0) + d];
+                for (int d = 0; d < 3; ++d) sr.x[d] = buf[P3 * (size_t)(n - n0) + d];
                 StageRec rec;
-                rk4_step_rec<DT, MODE>(a.g, a.f[n], a.f[n + 1], a.h[n], sr, rec);
+                rk4_step_rec<DT, MODE>(a.g, in_global(a.f[n]), in_global(a.f[n + 1]), a.h[n], sr, rec);
                 const float h = (float)a.h[n];
 #pragma unroll
                 for (int c = 0; c < NCOT; ++c) {
@@ -280,8 +303,8 @@ __global__ __launch_bounds__(BLOCK) void ftle_kernel(const float* jac, int64_t P
 // ---------------------------------------------------------------------------
 template <int DT, int MODE, int NCOT>
 static hipError_t launch_adj_t(const AdjointArgs& a, hipStream_t s) {
-    const int64_t blocks = (a.P + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL((adjoint_kernel<DT, MODE, NCOT>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, a);
+    const int64_t blocks = (a.P + ADJ_BLOCK - 1) / ADJ_BLOCK;
+    hipLaunchKernelGGL((adjoint_kernel<DT, MODE, NCOT>), dim3((unsigned)blocks), dim3(ADJ_BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

@@ -101,8 +101,8 @@ struct AdjointArgs {
     const float* cot;           // P x ncot x 3, d L / d x_end (world)
     float* grad_seed;           // P x ncot x 3, d L / d x_0 (world)
     float* const* grad_f;       // device array of N + 1 FP32 grids (accumulated) or null
-    double* ckpt;               // P x ceil(N/k) x 3 scratch
-    double* buf;                // P x k x 3 scratch
+    double* ckpt;               // ceil(N/k) x P x 3 scratch (slot-major)
+    double* buf;                // k x P x 3 scratch (slot-major)
     uint8_t* status_out;        // P (may be null): status of the recomputed forward
 };
 
