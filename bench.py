@@ -297,6 +297,52 @@ def precision_statement(log, threads):
     return out
 
 
+def per_cycle(log):
+    """One RK4 step per launch (the in situ call form) on three ABC blocks:
+    128^3 at stride 2 and 64^3 at strides 2 and 1, 100 cycles each, HIP events
+    around the 100 calls (mean per cycle over 4 repetitions).  The 64^3 block
+    at stride 1 has as many particles as the 128^3 block at stride 2 but an
+    eighth of the field bytes."""
+    import math
+    import torch
+    from bto_inputs import fields
+    from bto_inputs.workloads import WORKLOADS
+    from paper_2004_02003_amd import Context, grid_to_device
+
+    def run(n, stride, dev, times, reps=4):
+        with Context((n, n, n), n ** 3) as ctx:
+            ptrs = [g.data_ptr() for g in dev]
+            N = len(dev) - 1
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for r in range(reps + 1):
+                ctx.seed(stride)
+                if r >= 1:
+                    ev[r - 1][0].record()
+                for q in range(N):
+                    ctx.advect_ptrs(ptrs[q:q + 2], times[q:q + 2], 0)
+                if r >= 1:
+                    ev[r - 1][1].record()
+            torch.cuda.synchronize()
+            ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+            return {"seeds": ctx.n_seeds, "us_per_cycle": round(1e3 * ms / N, 2),
+                    "particle_steps": int(ctx.stats()["particle_steps"])}
+
+    out = {}
+    s = WORKLOADS["abc_128"].make_field()
+    dev = [grid_to_device(g, "f32") for g in s.grids("f32")]
+    out["abc_128_stride2"] = run(128, 2, dev, list(s.times))
+    del dev
+    s2 = fields.abc_noise(64, 101, 2 * math.pi / 1000, sigma=0.0, global_n=256, offset=(64, 64, 64))
+    dev2 = [grid_to_device(g, "f32") for g in s2.grids("f32")]
+    out["abc_64_stride2"] = run(64, 2, dev2, list(s2.times))
+    out["abc_64_stride1"] = run(64, 1, dev2, list(s2.times))
+    for k, v in out.items():
+        log(f"per cycle {k}: {v['us_per_cycle']} us")
+    del dev2
+    torch.cuda.empty_cache()
+    return out
+
+
 def differentiation(log):
     """The differentiation workload: 32^3 seeds (stride 4) on the 128^3 ABC
     field, 100 steps, checkpoints every 10.  Times (HIP events, median of 5)
@@ -359,6 +405,17 @@ def differentiation(log):
     return out
 
 
+# Legs that --leg runs on their own (all of them but per_cycle are part of the
+# default run on the abc_128 workload).
+LEGS = {
+    "paper_context": paper_context,
+    "posthoc_accuracy": posthoc_accuracy,
+    "insitu_overlap": lambda log: [insitu_overlap(log, 128, 32), insitu_overlap(log, 256, 64)],
+    "differentiation": differentiation,
+    "per_cycle": per_cycle,
+}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,6 +433,8 @@ def main(argv=None):
                     help="FP32 grids: lanes per particle (default per workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--leg", action="append", choices=sorted(LEGS),
+                    help="run only these legs (repeatable) and print their results as one JSON line")
     args = ap.parse_args(argv)
     if args.steps_per_launch is not None:
         os.environ["BTO_STEPS_PER_LAUNCH"] = str(args.steps_per_launch)
@@ -383,6 +442,15 @@ def main(argv=None):
         print("bench.py runs on exactly one GPU: the per-block BTO path has no cross-GPU work "
               "(blocks are independent); run one process per block instead.", file=sys.stderr)
         sys.exit(2)
+
+    if args.leg:
+        import torch
+        from paper_2004_02003_amd import _lib
+
+        _lib.load()
+        assert torch.cuda.is_available(), "bench.py needs a HIP device"
+        print(json.dumps({name: LEGS[name](log) for name in args.leg}), flush=True)
+        return
 
     import torch
     import oracle

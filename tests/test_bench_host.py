@@ -44,8 +44,16 @@ def test_launch_shapes_and_tables_are_consistent(bench):
     assert set(bench.PAPER_ABC_TABLE_MS) == {(i, s) for i in (25, 50, 100) for s in (1, 2, 3)}
     assert set(bench.UNIT_ROUNDOFF) == {"f32", "f16", "bf16"}
     for fn in ("paper_context", "posthoc_accuracy", "insitu_overlap", "precision_statement", "differentiation",
-               "kernel_hash", "main"):
+               "per_cycle", "kernel_hash", "main"):
         assert callable(getattr(bench, fn)), fn
+    assert set(bench.LEGS) == {"paper_context", "posthoc_accuracy", "insitu_overlap", "differentiation", "per_cycle"}
+    assert all(callable(f) for f in bench.LEGS.values())
+
+
+def test_unknown_leg_is_refused(bench):
+    with pytest.raises(SystemExit) as e:
+        bench.main(["--leg", "no_such_leg"])
+    assert e.value.code == 2
 
 
 def test_more_than_one_gpu_is_refused(bench):
