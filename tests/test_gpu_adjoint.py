@@ -251,3 +251,34 @@ def test_adjoint_on_16bit_grids_matches_oracle(dt):
     assert valid.sum() > 20
     err = np.linalg.norm(g[valid] - go[valid]) / np.linalg.norm(go[valid])
     assert err < 1e-5, err
+
+
+def test_jacobian_and_ftle_of_hyperbolic_strain_closed_form():
+    """Steady strain u = (a (x - c), -a (y - c), 0): the flow-map Jacobian of
+    RK4 is diag(R(a h)^N, R(-a h)^N, 1), R the RK4 amplification factor, and
+    the FTLE is ln R(a h) / h for every seed (independent of the oracle)."""
+    import torch
+    from paper_2004_02003_amd import Context, jacobian_ftle
+
+    n = (33, 33, 9)
+    c, a, h, N = 16.0, 0.2, 0.1, 25
+    times = np.arange(N + 1) * h
+    z_, y_, x_ = np.meshgrid(np.arange(n[2], dtype=float), np.arange(n[1], dtype=float),
+                             np.arange(n[0], dtype=float), indexing="ij")
+    g = np.stack([a * (x_ - c), -a * (y_ - c), np.zeros_like(x_)], axis=-1).astype(np.float32)
+    rng = np.random.default_rng(5)
+    seeds = np.stack([c + rng.uniform(-5, 5, 200), c + rng.uniform(-10, 10, 200), rng.uniform(1, 7, 200)], axis=1)
+    _say("jacobian of hyperbolic strain")
+    dev = _dev([g] * (N + 1))
+    with Context(n, len(seeds)) as ctx:
+        J, sig, st = jacobian_ftle(ctx, torch.as_tensor(seeds, device="cuda"), dev, times, ckpt_every=10)
+        torch.cuda.synchronize()
+        J, sig, st = J.cpu().numpy(), sig.cpu().numpy(), st.cpu().numpy()
+
+    def R(z):
+        return 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+
+    assert np.all(st == 0)
+    Jw = np.diag([R(a * h) ** N, R(-a * h) ** N, 1.0])
+    assert np.abs(J - Jw).max() < 1e-5
+    np.testing.assert_allclose(sig, np.log(R(a * h)) / h, rtol=1e-5)

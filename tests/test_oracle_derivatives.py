@@ -122,3 +122,48 @@ def test_uniform_flow_grid_gradient_closed_form():
     for c in range(N + 1):
         wt = (h[c - 1] / 2 if c > 0 else 0.0) + (h[c] / 2 if c < N else 0.0)
         np.testing.assert_allclose(gg[c].reshape(-1, 3).sum(0), wt * lam[0], atol=1e-14)
+
+
+def test_ftle_definition_on_known_singular_values():
+    """sigma = ln(largest singular value of J) / |T| for J = Q1 diag(s) Q2 with
+    orthogonal Q1, Q2 (and 0 for a rotation)."""
+    rng = np.random.default_rng(11)
+    Q1, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    s = np.array([0.3, 4.5, 1.7])
+    J = (Q1 @ np.diag(s) @ Q2)[None]
+    T = 2.5
+    np.testing.assert_allclose(oracle.ftle(J, T), np.log(4.5) / T, rtol=1e-13)
+    np.testing.assert_allclose(oracle.ftle(J, -T), np.log(4.5) / T, rtol=1e-13)
+    np.testing.assert_allclose(oracle.ftle(Q1[None], T), 0.0, atol=1e-14)
+
+
+def test_jacobian_and_ftle_of_hyperbolic_strain_closed_form():
+    """Steady strain u = (a (x - c), -a (y - c), 0) is linear in space, so the
+    trilinear sampler is exact and every RK4 step multiplies the offsets by
+    the amplification factor R(+-a h) = 1 + z + z^2/2 + z^3/6 + z^4/24: the
+    flow-map Jacobian is diag(R(a h)^N, R(-a h)^N, 1) and the FTLE is
+    ln R(a h) / h, independent of the seed."""
+    n = (33, 33, 9)
+    c, a, h, N = 16.0, 0.2, 0.1, 25
+    times = np.arange(N + 1) * h
+    z_, y_, x_ = np.meshgrid(np.arange(n[2], dtype=float), np.arange(n[1], dtype=float),
+                             np.arange(n[0], dtype=float), indexing="ij")
+    g = np.stack([a * (x_ - c), -a * (y_ - c), np.zeros_like(x_)], axis=-1)
+    F = oracle.Field(n, [g] * (N + 1))
+    rng = np.random.default_rng(5)
+    seeds = np.stack([c + rng.uniform(-5, 5, 40), c + rng.uniform(-10, 10, 40), rng.uniform(1, 7, 40)], axis=1)
+    r = oracle.flowmap(F, times, seeds, N, jac=True)
+    assert np.all(r["flag"] == 0)
+
+    def R(z):
+        return 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+
+    gx, gy = R(a * h) ** N, R(-a * h) ** N
+    np.testing.assert_allclose(r["end"][:, 0], c + (seeds[:, 0] - c) * gx, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["end"][:, 1], c + (seeds[:, 1] - c) * gy, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["end"][:, 2], seeds[:, 2], rtol=0, atol=1e-13)
+    Jw = np.zeros((3, 3))
+    Jw[0, 0], Jw[1, 1], Jw[2, 2] = gx, gy, 1.0
+    np.testing.assert_allclose(r["jac"], np.broadcast_to(Jw, r["jac"].shape), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(oracle.ftle(r["jac"], N * h), np.log(R(a * h)) / h, rtol=1e-12)
