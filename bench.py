@@ -406,8 +406,23 @@ def differentiation(log):
             ctx.seed(wl.stride)
             ctx.adjoint(dev, s.times, w, ckpt_every=1)
 
+        def forward_then_adjoint():
+            # the training-loop form: the forward advection, then the adjoint recomputing it
+            ctx.seed(wl.stride)
+            ctx.advect(dev, s.times)
+            ctx.adjoint(dev, s.times, w, ckpt_every=k)
+
+        def forward_recording_then_adjoint():
+            # the same with checkpoints recorded by the forward advection (no recomputed forward)
+            ctx.seed(wl.stride)
+            ctx.advect(dev, s.times, record_ckpt=True)
+            ctx.adjoint(dev, s.times, w, ckpt_every=k, recorded=True)
+
+        ctx.set_tuning(ckpt_every=k)
         for name, fn in (("seed_gradient", seed_grad), ("seed_and_grid_gradient", seed_and_grid_grad),
-                         ("jacobian_ftle", jac), ("seed_gradient_checkpoint_every_step", seed_grad_every_step)):
+                         ("jacobian_ftle", jac), ("seed_gradient_checkpoint_every_step", seed_grad_every_step),
+                         ("forward_then_seed_gradient", forward_then_adjoint),
+                         ("forward_recording_checkpoints_then_seed_gradient", forward_recording_then_adjoint)):
             ms = timed(fn)
             out[name] = {"ms": round(ms, 4), "forward_particle_steps_per_s": round(psteps / (ms * 1e-3), 1)}
             log(f"differentiation {name}: {ms:.3f} ms")

@@ -65,6 +65,18 @@ enum { BTO_TIME_LINEAR = 0, BTO_TIME_FROZEN = 1 };
  * percent of advection throughput. */
 enum { BTO_RECORD_EXIT = 2 };
 
+/* Flag bit of bto_advect_interval and bto_adjoint_interval.  On advection:
+ * record checkpoints for the adjoint -- the FP64 position (cell units) of
+ * every live particle at each step of the interval that is a multiple of the
+ * tuning's ckpt_every (counted from the seeding), taken at launch boundaries
+ * (launches are cut so that one starts at each such step).  The context holds
+ * ceil(steps / ckpt_every) x max_particles x 24 bytes for them, grown on demand
+ * (a growth synchronizes `stream`).  On the adjoint: take the forward
+ * trajectory from those checkpoints and the recorded flags instead of
+ * recomputing it (every advect call of the interval must have recorded, with
+ * one ckpt_every). */
+enum { BTO_RECORD_CKPT = 1 << 4 };
+
 /* Per-seed outcome in the flow map. */
 enum { BTO_VALID = 0, BTO_TERMINATED = 1, BTO_INVALID = 2 };
 
@@ -114,7 +126,8 @@ int bto_seed_explicit(bto_ctx *ctx, const double *d_xyz, int64_t n, void *stream
  * times; step s uses h = times[s+1] - times[s].  May be called repeatedly
  * within one interval (e.g. once per cycle with two grids): steps accumulate
  * and exit steps count from the seeding.  flags: BTO_TIME_LINEAR or
- * BTO_TIME_FROZEN, optionally | BTO_RECORD_EXIT.  Termination rule: the stage points y2, y3, y4 and the
+ * BTO_TIME_FROZEN, optionally | BTO_RECORD_EXIT and | BTO_RECORD_CKPT.
+ * Termination rule: the stage points y2, y3, y4 and the
  * step's end point are tested in that order; the first outside the block
  * terminates the particle in that step with its position frozen at the last
  * inside position; a non-finite velocity sample flags it INVALID likewise. */
@@ -149,7 +162,7 @@ int bto_exit_points(bto_ctx *ctx, double *d_exit_xyz, void *stream);
 int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
 
 /* Launch-shape tuning of the advection (none of it changes which events
- * happen; end positions agree to FP32 rounding):
+ * happen; end positions agree to FP32 rounding), and the checkpoint spacing:
  *   steps_per_launch    RK4 steps fused into one kernel launch, 1..128
  *                       (default 32; launches are balanced to equal lengths);
  *   rebin_every         re-sort the live particles by 32x2x2-cell bin, bins in
@@ -163,7 +176,9 @@ int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
  *                       the cache lines a wavefront touches per row load at the
  *                       cost of doubled per-particle ALU work, which pays on
  *                       incoherent (mixed) particle sets.  16-bit storage
- *                       always uses 1.
+ *                       always uses 1;
+ *   ckpt_every          steps between the checkpoints that BTO_RECORD_CKPT
+ *                       records (>= 1, default 10).
  * Defaults come from the environment variables BTO_STEPS_PER_LAUNCH,
  * BTO_REBIN_EVERY, BTO_BLOCKS_PER_CU and BTO_LANES_PER_PARTICLE when the
  * context is created.  BTO_EINVAL for values out of range; takes effect on
@@ -173,6 +188,7 @@ typedef struct {
     int32_t rebin_every;
     int32_t blocks_per_cu;
     int32_t lanes_per_particle;
+    int32_t ckpt_every;
 } bto_tuning;
 
 int bto_set_tuning(bto_ctx *ctx, const bto_tuning *t);
@@ -199,6 +215,13 @@ int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
  *              deterministic).  Only with n_cot = 1.
  *   d_status (n_seeds bytes, may be NULL): BTO_VALID / BTO_TERMINATED /
  *              BTO_INVALID from the recomputed forward.
+ * flags: BTO_TIME_LINEAR or BTO_TIME_FROZEN, optionally | BTO_RECORD_CKPT:
+ * then the forward pass is not recomputed; the checkpoints and flags that the
+ * interval's advection recorded are used (the grids, times and mode must be
+ * those of that advection).  BTO_ESTATE unless every advect call since the
+ * seeding recorded with one ckpt_every; BTO_EINVAL unless n_steps equals the
+ * steps advected and ckpt_every the recorded spacing.  d_status then holds
+ * the recorded flags.
  * Seeds that do not stay inside the block for the whole interval contribute
  * nothing: their gradient rows are zero.  Scratch of about
  * n_seeds * (n_steps / ckpt_every + ckpt_every) * 24 bytes is held by the

@@ -18,6 +18,7 @@ BTO_OK, BTO_EINVAL, BTO_ENOMEM, BTO_EHIP, BTO_ESTATE, BTO_ERANGE = 0, -1, -2, -3
 BTO_F32, BTO_F16, BTO_BF16 = 0, 1, 2
 BTO_TIME_LINEAR, BTO_TIME_FROZEN = 0, 1
 BTO_RECORD_EXIT = 2
+BTO_RECORD_CKPT = 1 << 4
 BTO_VALID, BTO_TERMINATED, BTO_INVALID = 0, 1, 2
 
 EXPORTED = [
@@ -44,7 +45,8 @@ class Block(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("steps_per_launch", ctypes.c_int32), ("rebin_every", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("lanes_per_particle", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("lanes_per_particle", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -1,10 +1,13 @@
 """Differentiable flow map: ``torch.autograd.Function`` over the C-ABI.
 
 Forward: seed the given positions, advance them through the grids (one RK4
-step per cycle, boundary termination) and return the end positions with their
-flags.  Backward: the library's discrete adjoint with checkpoints (gradients
+step per cycle, boundary termination, checkpoints recorded every
+``ckpt_every`` steps) and return the end positions with their flags.
+Backward: the library's discrete adjoint from those checkpoints (gradients
 with respect to the seed positions and, when the grids require grad, the
-grids).  Seeds that leave the block contribute nothing to the gradients.
+grids); if the context has been reseeded or advanced since the forward, the
+adjoint reseeds and recomputes the forward itself.  Seeds that leave the
+block contribute nothing to the gradients.
 """
 
 from __future__ import annotations
@@ -20,7 +23,13 @@ class BTOAdvectFn(torch.autograd.Function):
     def forward(fctx, bctx: Context, seeds: torch.Tensor, times, mode: str, ckpt_every: int, *grids):
         s = seeds.detach().to(torch.float64).contiguous()
         bctx.seed_explicit(s)
-        bctx.advect(list(grids), times, mode=mode)
+        k_prev = bctx.tuning()["ckpt_every"]
+        bctx.set_tuning(ckpt_every=int(ckpt_every))
+        try:
+            bctx.advect(list(grids), times, mode=mode, record_ckpt=True)
+        finally:
+            bctx.set_tuning(ckpt_every=k_prev)
+        fctx.serial = (bctx.interval_serial, bctx.steps_advected)
         fm = bctx.flowmap(with_seeds=False)
         fctx.bctx = bctx
         fctx.times = np.asarray(times, dtype=np.float64)
@@ -35,11 +44,14 @@ class BTOAdvectFn(torch.autograd.Function):
     def backward(fctx, g_end, g_flag, g_exit):
         s, *grids = fctx.saved_tensors
         bctx = fctx.bctx
-        bctx.seed_explicit(s)
+        recorded = (bctx.interval_serial, bctx.steps_advected) == fctx.serial
+        if not recorded:
+            bctx.seed_explicit(s)
         want_grids = any(fctx.needs_input_grad[5:])
         gg = [torch.zeros(g.shape, dtype=torch.float32, device=g.device) for g in grids] if want_grids else None
         cot = g_end.to(torch.float32).contiguous()
-        gs = bctx.adjoint(grids, fctx.times, cot, grad_grids=gg, ckpt_every=fctx.ckpt_every, mode=fctx.mode)
+        gs = bctx.adjoint(grids, fctx.times, cot, grad_grids=gg, ckpt_every=fctx.ckpt_every, mode=fctx.mode,
+                          recorded=recorded)
         g_seed = gs.view(-1, 3).to(fctx.seed_dtype) if fctx.needs_input_grad[1] else None
         g_grids = [g.to(v.dtype) for g, v in zip(gg, grids)] if want_grids else [None] * len(grids)
         return (None, g_seed, None, None, None, *g_grids)

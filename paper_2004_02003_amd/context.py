@@ -20,8 +20,9 @@ _TORCH_DT = {torch.float32: _lib.BTO_F32, torch.float16: _lib.BTO_F16, torch.bfl
 _MODES = {"linear": _lib.BTO_TIME_LINEAR, "frozen": _lib.BTO_TIME_FROZEN}
 
 
-def _flags(mode: str, record_exit: bool) -> int:
-    return _MODES[mode] | (_lib.BTO_RECORD_EXIT if record_exit else 0)
+def _flags(mode: str, record_exit: bool = False, record_ckpt: bool = False) -> int:
+    return (_MODES[mode] | (_lib.BTO_RECORD_EXIT if record_exit else 0)
+            | (_lib.BTO_RECORD_CKPT if record_ckpt else 0))
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -91,12 +92,13 @@ class Context:
         t = _lib.Tuning()
         self._check(self.L.bto_get_tuning(self._h, ctypes.byref(t)))
         return dict(steps_per_launch=t.steps_per_launch, rebin_every=t.rebin_every,
-                    blocks_per_cu=t.blocks_per_cu, lanes_per_particle=t.lanes_per_particle)
+                    blocks_per_cu=t.blocks_per_cu, lanes_per_particle=t.lanes_per_particle,
+                    ckpt_every=t.ckpt_every)
 
     def set_tuning(self, steps_per_launch=None, rebin_every=None, blocks_per_cu=None,
-                   lanes_per_particle=None):
+                   lanes_per_particle=None, ckpt_every=None):
         """Launch shape of the advection (events unchanged; positions agree
-        to FP32 rounding)."""
+        to FP32 rounding) and the spacing of recorded checkpoints."""
         cur = self.tuning()
         t = _lib.Tuning()
         t.steps_per_launch = cur["steps_per_launch"] if steps_per_launch is None else int(steps_per_launch)
@@ -104,6 +106,7 @@ class Context:
         t.blocks_per_cu = cur["blocks_per_cu"] if blocks_per_cu is None else int(blocks_per_cu)
         t.lanes_per_particle = (cur["lanes_per_particle"] if lanes_per_particle is None
                                 else int(lanes_per_particle))
+        t.ckpt_every = cur["ckpt_every"] if ckpt_every is None else int(ckpt_every)
         self._check(self.L.bto_set_tuning(self._h, ctypes.byref(t)))
 
     # -- the path ----------------------------------------------------------
@@ -112,20 +115,28 @@ class Context:
         P = ctypes.c_int64()
         self._check(self.L.bto_seed(self._h, int(stride), off, ctypes.byref(P), _stream_ptr(stream)))
         self.n_seeds = int(P.value)
+        self._new_interval()
         return self.n_seeds
+
+    def _new_interval(self):
+        # host-side bookkeeping of the interval (which one, steps advanced so far)
+        self.interval_serial = getattr(self, "interval_serial", 0) + 1
+        self.steps_advected = 0
 
     def seed_explicit(self, xyz: torch.Tensor, stream=None) -> int:
         if xyz.dtype != torch.float64 or xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
             raise ValueError("seeds must be a contiguous (n, 3) float64 device tensor")
         self._check(self.L.bto_seed_explicit(self._h, xyz.data_ptr(), int(xyz.shape[0]), _stream_ptr(stream)))
         self.n_seeds = int(xyz.shape[0])
+        self._new_interval()
         return self.n_seeds
 
     def advect(self, grids: Sequence[torch.Tensor], times, mode: str = "linear", record_exit: bool = False,
-               stream=None):
+               stream=None, record_ckpt: bool = False):
         """n = len(grids) - 1 RK4 steps through the given consecutive cycles;
         ``record_exit`` keeps the exit point of every particle terminated here
-        (``exit_points``)."""
+        (``exit_points``); ``record_ckpt`` records checkpoints every
+        ``tuning()["ckpt_every"]`` steps for ``adjoint(..., recorded=True)``."""
         if len(grids) < 2:
             raise ValueError("need at least two grids (one step)")
         dt = grids[0].dtype
@@ -140,14 +151,18 @@ class Context:
             raise ValueError("one time per grid")
         ptrs = (ctypes.c_void_p * len(grids))(*[g.data_ptr() for g in grids])
         self._check(self.L.bto_advect_interval(self._h, ptrs, times.ctypes.data, len(grids) - 1,
-                                               _TORCH_DT[dt], _flags(mode, record_exit), _stream_ptr(stream)))
+                                               _TORCH_DT[dt], _flags(mode, record_exit, record_ckpt),
+                                               _stream_ptr(stream)))
+        self.steps_advected = getattr(self, "steps_advected", 0) + len(grids) - 1
 
-    def advect_ptrs(self, ptrs, times, dtype: int, mode: str = "linear", record_exit: bool = False, stream=None):
+    def advect_ptrs(self, ptrs, times, dtype: int, mode: str = "linear", record_exit: bool = False, stream=None,
+                    record_ckpt: bool = False):
         """Same as ``advect`` with raw device pointers (no per-call tensor checks)."""
         arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
         t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
         self._check(self.L.bto_advect_interval(self._h, arr, t.ctypes.data, len(ptrs) - 1, int(dtype),
-                                               _flags(mode, record_exit), _stream_ptr(stream)))
+                                               _flags(mode, record_exit, record_ckpt), _stream_ptr(stream)))
+        self.steps_advected = getattr(self, "steps_advected", 0) + len(ptrs) - 1
 
     def flowmap(self, with_seeds: bool = True, count_valid: bool = False, out=None, stream=None):
         """Seed-ordered flow map: dict with end (P,3) f64, flag (P,) u8,
@@ -181,9 +196,12 @@ class Context:
 
     def adjoint(self, grids: Sequence[torch.Tensor], times, cot: torch.Tensor, grad_grids=None,
                 ckpt_every: int = 10, mode: str = "linear", status: Optional[torch.Tensor] = None,
-                stream=None) -> torch.Tensor:
+                stream=None, recorded: bool = False) -> torch.Tensor:
         """Gradients d(cot . x_end)/d x_0 for the current seeds (n_cot = cot.shape[1]
         cotangent vectors per seed; 3 unit cotangents give the Jacobian rows).
+        ``recorded``: take the forward trajectory from the checkpoints that the
+        interval's advection recorded (``advect(..., record_ckpt=True)``, same
+        grids, times and mode) instead of recomputing it.
         ``grad_grids`` (optional list of float32 tensors shaped like the grids)
         receive d L / d V added in place."""
         P = self.n_seeds
@@ -207,7 +225,8 @@ class Context:
                     raise ValueError("grad grids must be contiguous float32 tensors shaped like the grids")
             gptr = (ctypes.c_void_p * len(grad_grids))(*[g.data_ptr() for g in grad_grids])
         self._check(self.L.bto_adjoint_interval(
-            self._h, ptrs, times.ctypes.data, len(grids) - 1, _TORCH_DT[dt], _MODES[mode], cot.data_ptr(), ncot,
+            self._h, ptrs, times.ctypes.data, len(grids) - 1, _TORCH_DT[dt], _flags(mode, record_ckpt=recorded),
+            cot.data_ptr(), ncot,
             out.data_ptr(), gptr, status.data_ptr() if status is not None else None, int(ckpt_every),
             _stream_ptr(stream)))
         return out

@@ -3,7 +3,9 @@
 // the FTLE of flow-map Jacobians.
 //
 // One lane per seed.  Forward: the same RK4 stepping as the advection kernel,
-// storing the FP64 position every `k` steps (checkpoints).  Backward: for each
+// storing the FP64 position every `k` steps (checkpoints) -- or none at all
+// when the advection recorded the checkpoints (then the per-seed records give
+// which seeds stayed inside for the whole interval).  Backward: for each
 // k-step segment in reverse, recompute its steps from the checkpoint (storing
 // each step's start), then walk them backwards: recompute the four stage
 // points with the sampler gradients G_s (on the cell chosen by the floor/clamp
@@ -167,20 +169,29 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a)
     // checkpoints and recomputed step starts, slot-major ([slot][seed][xyz]), so a
     // wavefront's 64 positions of one slot are one contiguous 1.5 KB run
     const size_t P3 = (size_t)a.P * 3;
+    const size_t CK = (size_t)a.ck_stride;
     double* ck = a.ckpt + (size_t)p * 3;
     double* buf = a.buf + (size_t)p * 3;
 
     Stepper<DT> st;
     stepper_init(st);
+    int status;
+    if (a.rec_meta) {
+        // forward recorded by the advection: its checkpoints are in place and
+        // the record says whether the seed stayed inside for the whole interval
+        const int32_t meta = a.rec_meta[p];
+        status = meta == META_LIVE ? S_VALID : (int)((uint32_t)meta >> META_SHIFT);
+    } else {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) st.x[d] = (a.seed_xyz[3 * p + d] - a.origin[d]) * a.g.inv_sp[d];
-    int status = inside(a.g, st.x) ? S_VALID : S_TERMINATED;
-    for (int n = 0; n < N && status == S_VALID; ++n) {
-        if (n % K == 0) {
+        for (int d = 0; d < 3; ++d) st.x[d] = (a.seed_xyz[3 * p + d] - a.origin[d]) * a.g.inv_sp[d];
+        status = inside(a.g, st.x) ? S_VALID : S_TERMINATED;
+        for (int n = 0; n < N && status == S_VALID; ++n) {
+            if (n % K == 0) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) ck[P3 * (size_t)(n / K) + d] = st.x[d];
+                for (int d = 0; d < 3; ++d) ck[CK * (size_t)(n / K) + d] = st.x[d];
+            }
+            status = rk4_step_alt<DT, MODE>(a.g, in_global(a.f[n]), in_global(a.f[n + 1]), a.h[n], n, st);
         }
-        status = rk4_step_alt<DT, MODE>(a.g, in_global(a.f[n]), in_global(a.f[n + 1]), a.h[n], n, st);
     }
     if (a.status_out) a.status_out[p] = (uint8_t)status;
 
@@ -200,7 +211,7 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a)
             const int n1 = (n0 + K < N) ? n0 + K : N;
             stepper_init(st);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) st.x[d] = ck[P3 * (size_t)sg + d];
+            for (int d = 0; d < 3; ++d) st.x[d] = ck[CK * (size_t)sg + d];
             for (int n = n0; n < n1; ++n) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) buf[P3 * (size_t)(n - n0) + d] = st.x[d];

@@ -56,6 +56,12 @@ struct bto_ctx {
     // adjoint scratch (grown on demand)
     void* adj_scratch = nullptr;
     size_t adj_bytes = 0;
+    // checkpoints recorded by BTO_RECORD_CKPT advection: ck_slots slots of cap x 3 doubles
+    int ckpt_every = 10;          // tuning: spacing of recorded checkpoints
+    double* ck_rec = nullptr;
+    int64_t ck_slots = 0;
+    int ck_k = 0;                 // spacing recorded in this interval (0: nothing advected yet)
+    bool ck_ok = false;           // every advect call since the seeding recorded, with spacing ck_k
     std::string err;
 };
 
@@ -182,6 +188,7 @@ int bto_destroy(bto_ctx* c) {
     if (c->seed_xyz) (void)hipFree(c->seed_xyz);
     if (c->counts) (void)hipFree(c->counts);
     if (c->adj_scratch) (void)hipFree(c->adj_scratch);
+    if (c->ck_rec) (void)hipFree(c->ck_rec);
     if (c->rebin_buf) (void)hipFree(c->rebin_buf);
     if (c->rebin_temp) (void)hipFree(c->rebin_temp);
     delete c;
@@ -210,6 +217,36 @@ static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hip
     c->n_seeds = P;
     c->steps_done = 0;
     c->steps_since_rebin = 0;
+    c->ck_k = 0;
+    c->ck_ok = true;
+    return BTO_OK;
+}
+
+// Room for checkpoint slots 0 .. slots - 1 (keeps the recorded ones).
+static int ensure_ckpt_slots(bto_ctx* c, int64_t slots, hipStream_t s) {
+    if (slots <= c->ck_slots) return BTO_OK;
+    int64_t want = c->ck_slots * 2 > slots ? c->ck_slots * 2 : slots;
+    const size_t slot_bytes = (size_t)c->cap * 3 * sizeof(double);
+    double* nb = nullptr;
+    if (hipMalloc(&nb, (size_t)want * slot_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        want = slots;
+        if (hipMalloc(&nb, (size_t)want * slot_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, BTO_ENOMEM, "checkpoint record of %lld slots", (long long)slots);
+        }
+    }
+    if (c->ck_rec) {
+        hipError_t e = hipMemcpyAsync(nb, c->ck_rec, (size_t)c->ck_slots * slot_bytes, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            (void)hipFree(nb);
+            return hip_fail(c, e, "checkpoint record growth");
+        }
+        (void)hipFree(c->ck_rec);
+    }
+    c->ck_rec = nb;
+    c->ck_slots = want;
     return BTO_OK;
 }
 
@@ -355,10 +392,10 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     if (!d_fields || !times) return fail(c, BTO_EINVAL, "null field or time array");
     if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
     if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
-    if ((flags & ~BTO_RECORD_EXIT) != BTO_TIME_LINEAR && (flags & ~BTO_RECORD_EXIT) != BTO_TIME_FROZEN)
-        return fail(c, BTO_EINVAL, "unknown flags %d", flags);
-    const int mode = flags & ~BTO_RECORD_EXIT;
+    const int mode = flags & ~(BTO_RECORD_EXIT | BTO_RECORD_CKPT);
+    if (mode != BTO_TIME_LINEAR && mode != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
     const int rec = (flags & BTO_RECORD_EXIT) ? 1 : 0;
+    const bool rec_ck = (flags & BTO_RECORD_CKPT) != 0;
     for (int32_t q = 0; q <= n_steps; ++q)
         if (!d_fields[q]) return fail(c, BTO_EINVAL, "field pointer %d is null", q);
     for (int32_t q = 0; q < n_steps; ++q)
@@ -367,6 +404,18 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     if (!c->seeded) return fail(c, BTO_ESTATE, "advect called before seeding");
     if ((int64_t)c->steps_done + n_steps > META_STEP) return fail(c, BTO_ERANGE, "interval too long");
     hipStream_t s = (hipStream_t)stream;
+    // checkpoint record: complete only if every call of the interval records with one spacing
+    if (rec_ck) {
+        if (c->ck_k == 0) c->ck_k = c->ckpt_every;
+        if (c->ck_k != c->ckpt_every) c->ck_ok = false;
+    } else {
+        c->ck_ok = false;
+    }
+    const bool store_ck = rec_ck && c->ck_ok;
+    if (store_ck && c->n_seeds > 0) {
+        rc = ensure_ckpt_slots(c, ((int64_t)c->steps_done + n_steps - 1) / c->ck_k + 1, s);
+        if (rc) return rc;
+    }
     if (c->n_seeds == 0) {
         c->steps_done += n_steps;
         return BTO_OK;
@@ -381,11 +430,28 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     int kmax = c->steps_per_launch;
     if (c->rebin_every > 0 && c->rebin_every < kmax) kmax = c->rebin_every;
     const int nl = (n_steps + kmax - 1) / kmax;
-    for (int32_t l = 0, q0 = 0; l < nl; ++l) {
-        const int K = n_steps / nl + (l < n_steps % nl ? 1 : 0);
+    for (int32_t l = 0, q0 = 0; q0 < n_steps; ++l) {
+        int K = n_steps / nl + (l < n_steps % nl ? 1 : 0);
+        if (store_ck) {
+            // launches end at checkpoint steps; equal lengths between two of them
+            const int to_ck = c->ck_k - c->steps_done % c->ck_k;
+            const int seg = to_ck < n_steps - q0 ? to_ck : n_steps - q0;
+            const int parts = (seg + kmax - 1) / kmax;
+            K = (seg + parts - 1) / parts;
+        }
         if (c->rebin_every > 0 && c->steps_since_rebin >= c->rebin_every) {
             rc = rebin(c, s);
             if (rc) return rc;
+        }
+        if (store_ck && c->steps_done % c->ck_k == 0) {
+            CkptArgs ca{};
+            ca.segs = c->segs;
+            ca.count = c->counts + NSEG * c->slot;
+            ca.pos = c->pos[c->cur];
+            ca.id = c->id[c->cur];
+            ca.out = c->ck_rec + (size_t)(c->steps_done / c->ck_k) * (size_t)c->cap * 3;
+            hipError_t e = launch_ckpt_store(ca, blocks_per_seg(c, max_seg, 4), s);
+            if (e != hipSuccess) return hip_fail(c, e, "checkpoint store launch");
         }
         AdvectArgs a{};
         for (int q = 0; q <= K; ++q) a.f[q] = static_cast<const char*>(d_fields[q0 + q]);
@@ -554,7 +620,9 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
     if (!d_fields || !times || !d_cot_end || !d_grad_seed) return fail(c, BTO_EINVAL, "null argument");
     if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
     if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
-    if (flags != BTO_TIME_LINEAR && flags != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    const int mode = flags & ~BTO_RECORD_CKPT;
+    const bool use_ck = (flags & BTO_RECORD_CKPT) != 0;
+    if (mode != BTO_TIME_LINEAR && mode != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
     if (n_cot != 1 && n_cot != 3) return fail(c, BTO_EINVAL, "n_cot must be 1 or 3 (got %d)", n_cot);
     if (d_grad_fields && n_cot != 1) return fail(c, BTO_EINVAL, "grid gradients need n_cot == 1");
     if (ckpt_every < 1) return fail(c, BTO_EINVAL, "ckpt_every must be >= 1");
@@ -566,12 +634,21 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
         if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
             return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
     if (!c->seeded) return fail(c, BTO_ESTATE, "adjoint called before seeding");
+    if (use_ck) {
+        if (!c->ck_ok || c->ck_k == 0)
+            return fail(c, BTO_ESTATE, "no complete checkpoint record (advect every call of the interval with BTO_RECORD_CKPT)");
+        if (n_steps != c->steps_done)
+            return fail(c, BTO_EINVAL, "n_steps %d differs from the %d steps advected", n_steps, c->steps_done);
+        if (ckpt_every != c->ck_k)
+            return fail(c, BTO_EINVAL, "ckpt_every %d differs from the recorded spacing %d", ckpt_every, c->ck_k);
+    }
     if (c->n_seeds == 0) return BTO_OK;
     const int K = ckpt_every < n_steps ? ckpt_every : n_steps;
     const int nseg = (n_steps + K - 1) / K;
     const size_t P = (size_t)c->n_seeds;
     const size_t tab = ((size_t)(n_steps + 1) * 2 * sizeof(void*) + (size_t)n_steps * sizeof(double) + 255) & ~(size_t)255;
-    const size_t need = tab + P * 3 * sizeof(double) * ((size_t)nseg + (size_t)K);
+    // checkpoint slots live in the scratch unless they were recorded
+    const size_t need = tab + P * 3 * sizeof(double) * ((use_ck ? 0 : (size_t)nseg) + (size_t)K);
     hipStream_t s = (hipStream_t)stream;
     if (need > c->adj_bytes) {
         if (c->adj_scratch) {
@@ -616,10 +693,19 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
     }
     a.cot = d_cot_end;
     a.grad_seed = d_grad_seed;
-    a.ckpt = reinterpret_cast<double*>(base + tab);
-    a.buf = a.ckpt + P * 3 * (size_t)nseg;
+    if (use_ck) {
+        a.ckpt = c->ck_rec;
+        a.ck_stride = c->cap * 3;
+        a.buf = reinterpret_cast<double*>(base + tab);
+        a.rec_meta = c->rec_meta;
+    } else {
+        a.ckpt = reinterpret_cast<double*>(base + tab);
+        a.ck_stride = (int64_t)P * 3;
+        a.buf = a.ckpt + P * 3 * (size_t)nseg;
+        a.rec_meta = nullptr;
+    }
     a.status_out = d_status;
-    e = launch_adjoint(a, dtype, flags, s);
+    e = launch_adjoint(a, dtype, mode, s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
     return BTO_OK;
 }
@@ -643,7 +729,9 @@ int bto_set_tuning(bto_ctx* c, const bto_tuning* t) {
     if (t->blocks_per_cu < 0) return fail(c, BTO_EINVAL, "blocks_per_cu must be >= 0");
     if (t->lanes_per_particle != 1 && t->lanes_per_particle != 2)
         return fail(c, BTO_EINVAL, "lanes_per_particle must be 1 or 2");
+    if (t->ckpt_every < 1) return fail(c, BTO_EINVAL, "ckpt_every must be >= 1");
     c->lanes_per_particle = t->lanes_per_particle;
+    c->ckpt_every = t->ckpt_every;
     c->steps_per_launch = t->steps_per_launch;
     c->rebin_every = t->rebin_every;
     c->blocks_per_cu_cap = t->blocks_per_cu;
@@ -656,6 +744,7 @@ int bto_get_tuning(const bto_ctx* c, bto_tuning* t) {
     t->rebin_every = c->rebin_every;
     t->blocks_per_cu = c->blocks_per_cu_cap;
     t->lanes_per_particle = c->lanes_per_particle;
+    t->ckpt_every = c->ckpt_every;
     return BTO_OK;
 }
 

@@ -101,9 +101,21 @@ struct AdjointArgs {
     const float* cot;           // P x ncot x 3, d L / d x_end (world)
     float* grad_seed;           // P x ncot x 3, d L / d x_0 (world)
     float* const* grad_f;       // device array of N + 1 FP32 grids (accumulated) or null
-    double* ckpt;               // ceil(N/k) x P x 3 scratch (slot-major)
+    double* ckpt;               // ceil(N/k) slots of ck_stride doubles ([slot][seed][xyz], cell units)
+    int64_t ck_stride;          // doubles per checkpoint slot (>= 3 P)
     double* buf;                // k x P x 3 scratch (slot-major)
     uint8_t* status_out;        // P (may be null): status of the recomputed forward
+    const int32_t* rec_meta;    // non-null: take the forward from recorded checkpoints and these records
+};
+
+// Checkpoint of the live particles for the adjoint: FP64 positions (cell
+// units) by seed id into one slot.
+struct CkptArgs {
+    Segs segs;
+    const uint32_t* count;     // NSEG live counts
+    const PState* pos;
+    const uint32_t* id;
+    double* out;               // slot base: [seed id][xyz]
 };
 
 // Rebin bins: REBIN_BIN[0] x REBIN_BIN[1] x REBIN_BIN[2] cells, x fastest.
@@ -142,6 +154,7 @@ hipError_t launch_place(const int32_t mb[3], const int32_t M[3], const int32_t o
                         const double* src_xyz, const uint8_t* src_flag, double* dst_xyz, uint8_t* dst_flag,
                         hipStream_t s);
 hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t s);
+hipError_t launch_ckpt_store(const CkptArgs& a, int blocks_per_seg, hipStream_t s);
 int advect_max_blocks_per_cu(int dtype, int mode, int lanes_per_particle, int record_exit);
 hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s);

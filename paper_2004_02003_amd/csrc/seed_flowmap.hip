@@ -218,6 +218,29 @@ hipError_t launch_exit_points(const FlowmapArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Checkpoint of the live particles (recorded for the adjoint at the start of
+// a launch): the unpacked FP64 position, i.e. exactly the state the next
+// advection launch resumes from.
+__global__ __launch_bounds__(BLOCK) void ckpt_store_kernel(const CkptArgs a) {
+    const int seg = blockIdx.x % NSEG;
+    const int r = blockIdx.x / NSEG;
+    const int R = gridDim.x / NSEG;
+    const uint32_t cnt = a.count[seg];
+    const int64_t sbase = a.segs.base[seg];
+    for (uint32_t i = (uint32_t)r * BLOCK + threadIdx.x; i < cnt; i += (uint32_t)R * BLOCK) {
+        const uint32_t id = a.id[sbase + i];
+        double x[3];
+        unpack(a.pos[sbase + i], x);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a.out[3 * (size_t)id + d] = x[d];
+    }
+}
+
+hipError_t launch_ckpt_store(const CkptArgs& a, int R, hipStream_t s) {
+    hipLaunchKernelGGL(ckpt_store_kernel, dim3(R * NSEG), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_flowmap(const FlowmapArgs& a, int R, hipStream_t s) {
     hipLaunchKernelGGL(flowmap_records_kernel, dim3(grid_for(a.P)), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();

@@ -282,3 +282,62 @@ def test_jacobian_and_ftle_of_hyperbolic_strain_closed_form():
     Jw = np.diag([R(a * h) ** N, R(-a * h) ** N, 1.0])
     assert np.abs(J - Jw).max() < 1e-5
     np.testing.assert_allclose(sig, np.log(R(a * h)) / h, rtol=1e-5)
+
+
+def test_recorded_checkpoints_give_the_recomputed_gradients():
+    """Checkpoints recorded by the advection (two streaming calls, launches cut
+    at every 5th step) give the same seed and grid gradients and flags as the
+    adjoint's own recomputed forward; mismatched or incomplete records are
+    refused."""
+    import torch
+    from paper_2004_02003_amd import BTOError, Context
+
+    n, N, s, gr, seeds, w = _small()
+    dev = _dev(gr)
+    cot = torch.as_tensor(w, dtype=torch.float32, device="cuda").contiguous()
+    o = oracle.flowmap(oracle.Field(n, gr), s.times, seeds, N)
+    safe = o["margin"] > 1e-6
+    _say("recorded checkpoints")
+    with Context(n, len(seeds)) as ctx:
+        ctx.set_tuning(ckpt_every=5)
+        x0 = torch.as_tensor(seeds, dtype=torch.float64, device="cuda")
+        ctx.seed_explicit(x0)
+        ctx.advect(dev[:10], s.times[:10], record_ckpt=True)
+        ctx.advect(dev[9:], s.times[9:], record_ckpt=True)
+        fm = ctx.flowmap()
+        st_r = torch.empty(len(seeds), dtype=torch.uint8, device="cuda")
+        gg_r = [torch.zeros_like(g) for g in dev]
+        g_r = ctx.adjoint(dev, s.times, cot, grad_grids=gg_r, ckpt_every=5, status=st_r, recorded=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(st_r.cpu().numpy(), fm["flag"].cpu().numpy())
+        with pytest.raises(BTOError):
+            ctx.adjoint(dev, s.times, cot, ckpt_every=4, recorded=True)      # other spacing
+        with pytest.raises(BTOError):
+            ctx.adjoint(dev[:10], s.times[:10], cot, ckpt_every=5, recorded=True)  # other length
+        # the adjoint's own forward from the seeds
+        ctx.seed_explicit(x0)
+        st_c = torch.empty(len(seeds), dtype=torch.uint8, device="cuda")
+        gg_c = [torch.zeros_like(g) for g in dev]
+        g_c = ctx.adjoint(dev, s.times, cot, grad_grids=gg_c, ckpt_every=5, status=st_c)
+        torch.cuda.synchronize()
+        with pytest.raises(BTOError):   # reseeded, nothing recorded since
+            ctx.adjoint(dev, s.times, cot, ckpt_every=5, recorded=True)
+        ctx.advect(dev, s.times)
+        with pytest.raises(BTOError):   # advected without recording
+            ctx.adjoint(dev, s.times, cot, ckpt_every=5, recorded=True)
+        ctx.seed_explicit(x0)
+        ctx.advect(dev[:10], s.times[:10], record_ckpt=True)
+        ctx.set_tuning(ckpt_every=4)
+        ctx.advect(dev[9:], s.times[9:], record_ckpt=True)
+        with pytest.raises(BTOError):   # two spacings in one interval
+            ctx.adjoint(dev, s.times, cot, ckpt_every=5, recorded=True)
+    sr, sc = st_r.cpu().numpy(), st_c.cpu().numpy()
+    assert np.array_equal(sr[safe], sc[safe])
+    ok = safe & (sr == 0)
+    assert ok.sum() > 20
+    a, b = g_r.cpu().numpy().reshape(-1, 3)[ok], g_c.cpu().numpy().reshape(-1, 3)[ok]
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-5
+    if np.array_equal(sr, sc):  # grid gradients sum over every seed that stayed inside
+        ga = np.concatenate([g.cpu().numpy().ravel() for g in gg_r])
+        gb = np.concatenate([g.cpu().numpy().ravel() for g in gg_c])
+        assert np.linalg.norm(ga - gb) / np.linalg.norm(gb) < 1e-5
