@@ -79,3 +79,38 @@ def test_product_package_does_not_import_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", txt, flags=re.M), f
                 assert "bto_oracle" not in txt and "liboracle" not in txt, f
+
+
+def _header_constants():
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = {}
+    for body in re.findall(r"enum(?:\s+\w+)?\s*\{([^}]*)\}", txt):
+        for name, expr in re.findall(r"(BTO_[A-Z0-9_]+)\s*=\s*([^,]+)", body):
+            parts = [int(v) for v in expr.split("<<")]  # integer literals, optionally one shift
+            vals[name] = parts[0] << parts[1] if len(parts) == 2 else parts[0]
+    return vals
+
+
+def _header_struct_fields(name):
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + r"\s*;", txt).group(1)
+    return re.findall(r"\b(int32_t|int64_t|double)\s+([a-z_0-9]+)(?:\[(\d+)\])?\s*;", body)
+
+
+def test_python_binding_mirrors_the_header():
+    """Every constant and struct the binding marshals has the header's value
+    and field layout (names, types, order)."""
+    from paper_2004_02003_amd import _lib
+
+    consts = _header_constants()
+    for name in ("BTO_OK", "BTO_EINVAL", "BTO_ENOMEM", "BTO_EHIP", "BTO_ESTATE", "BTO_ERANGE", "BTO_F32",
+                 "BTO_F16", "BTO_BF16", "BTO_TIME_LINEAR", "BTO_TIME_FROZEN", "BTO_RECORD_EXIT", "BTO_RECORD_CKPT",
+                 "BTO_VALID", "BTO_TERMINATED", "BTO_INVALID"):
+        assert getattr(_lib, name) == consts[name], name
+    ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
+    for cname, py in (("bto_tuning", _lib.Tuning), ("bto_block", _lib.Block), ("bto_stats_t", _lib.Stats)):
+        want = [(f, ctype[t] * int(n) if n else ctype[t]) for t, f, n in _header_struct_fields(cname)]
+        got = list(py._fields_)
+        assert [f for f, _ in got] == [f for f, _ in want], cname
+        for (f, a), (_, b) in zip(got, want):
+            assert ctypes.sizeof(a) == ctypes.sizeof(b) and getattr(a, "_type_", a) == getattr(b, "_type_", b), (cname, f)
