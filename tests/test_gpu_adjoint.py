@@ -284,11 +284,13 @@ def test_jacobian_and_ftle_of_hyperbolic_strain_closed_form():
     np.testing.assert_allclose(sig, np.log(R(a * h)) / h, rtol=1e-5)
 
 
-def test_recorded_checkpoints_give_the_recomputed_gradients():
+@pytest.mark.parametrize("shape", [{}, {"rebin_every": 3, "lanes_per_particle": 2, "steps_per_launch": 4}])
+def test_recorded_checkpoints_give_the_recomputed_gradients(shape):
     """Checkpoints recorded by the advection (two streaming calls, launches cut
-    at every 5th step) give the same seed and grid gradients and flags as the
-    adjoint's own recomputed forward; mismatched or incomplete records are
-    refused."""
+    at every 5th step; also with re-sorting every 3 steps, two lanes per
+    particle and 4-step launches) give the same seed and grid gradients and
+    flags as the adjoint's own recomputed forward; mismatched or incomplete
+    records are refused."""
     import torch
     from paper_2004_02003_amd import BTOError, Context
 
@@ -297,9 +299,9 @@ def test_recorded_checkpoints_give_the_recomputed_gradients():
     cot = torch.as_tensor(w, dtype=torch.float32, device="cuda").contiguous()
     o = oracle.flowmap(oracle.Field(n, gr), s.times, seeds, N)
     safe = o["margin"] > 1e-6
-    _say("recorded checkpoints")
+    _say(f"recorded checkpoints {shape}")
     with Context(n, len(seeds)) as ctx:
-        ctx.set_tuning(ckpt_every=5)
+        ctx.set_tuning(ckpt_every=5, **shape)
         x0 = torch.as_tensor(seeds, dtype=torch.float64, device="cuda")
         ctx.seed_explicit(x0)
         ctx.advect(dev[:10], s.times[:10], record_ckpt=True)
