@@ -210,9 +210,15 @@ int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
  *              Jacobian dx_end/dx_0 per seed, row-major).
  *   d_grad_seed (n_seeds x n_cot x 3 floats): d L / d x_0 per cotangent.
  *   d_grad_fields: NULL, or a HOST array of n_steps + 1 device pointers to
- *              float32 grids shaped like the velocity grids; d L / d V_c is
- *              ADDED to them (FP32 atomics, summation order not
- *              deterministic).  Only with n_cot = 1.
+ *              distinct float32 grids shaped like the velocity grids;
+ *              d L / d V_c is ADDED to them.  Each particle's contributions
+ *              to one cell of one grid are summed, recorded, sorted by
+ *              (cell parity, grid, cell, seed) and added in that order, so
+ *              the result is deterministic; the call synchronizes `stream`
+ *              once more to size the sort.  Records beyond about 4 GiB (or
+ *              with BTO_GRAD_ATOMICS=1 in the environment at context
+ *              creation) are added with FP32 atomics instead, in no fixed
+ *              order.  Only with n_cot = 1.
  *   d_status (n_seeds bytes, may be NULL): BTO_VALID / BTO_TERMINATED /
  *              BTO_INVALID from the recomputed forward.
  * flags: BTO_TIME_LINEAR or BTO_TIME_FROZEN, optionally | BTO_RECORD_CKPT:

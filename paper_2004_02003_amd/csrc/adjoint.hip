@@ -10,8 +10,9 @@
 // each step's start), then walk them backwards: recompute the four stage
 // points with the sampler gradients G_s (on the cell chosen by the floor/clamp
 // rule) and apply the transposed stage recurrences to every cotangent vector.
-// Grid gradients are scattered with FP32 atomics (their summation order is
-// not deterministic).  Terminated and invalid seeds contribute nothing (the
+// Grid gradients leave as records for the sorted, deterministic reduction
+// (grad_reduce.hip), or as FP32 atomics when no record buffer is given (their
+// summation order is then not fixed).  Terminated and invalid seeds contribute nothing (the
 // loss covers only the basis flows that stay inside the block).
 #include "bto_internal.h"
 
@@ -98,19 +99,47 @@ __device__ __forceinline__ void gT(const float G[3][3], const float v[3], float 
 
 // Grid-gradient accumulator: the 8 corner gradients of one cell of one grid
 // level, summed in registers while consecutive stage contributions hit the
-// same cell and level, and added to the grid with atomics only when the cell
-// or level changes (and at the end of each checkpoint segment).  In the
-// reverse sweep a level receives its contributions from two consecutive
-// steps (level n from step n's first three stages and from step n-1's last
-// three), so a particle that stays in its cell flushes once per level.
+// same cell and level, and flushed only when the cell or level changes (and at
+// the end of each checkpoint segment).  In the reverse sweep a level receives
+// its contributions from two consecutive steps (level n from step n's first
+// three stages and from step n-1's last three), so a particle that stays in
+// its cell flushes once per level.  A flush appends a record for the sorted,
+// deterministic reduction (or, without records or when they are full, adds the
+// values to the grid with FP32 atomics).
 struct GradAcc {
     uint32_t base;
     int level;
     float v[8][3];
 };
 
-__device__ __forceinline__ void acc_flush(const Geom& g, float* const* gf, GradAcc& A) {
+__device__ __forceinline__ void acc_flush(const Geom& g, float* const* gf, const GradRec& R, uint32_t pid,
+                                          GradAcc& A) {
     if (A.base == NO_CELL) return;
+    if (R.key) {
+        // one counter atomic per wavefront and flush round
+        const unsigned long long act = __ballot(1);
+        const int lane = (int)__lane_id();
+        const int leader = __ffsll((long long)act) - 1;
+        uint32_t first = 0;
+        if (lane == leader) first = atomicAdd(R.count, (uint32_t)__popcll(act));
+        first = __shfl(first, leader);
+        const uint32_t slot = first + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+        if (slot < R.cap) {
+            const uint32_t i = A.base % g.sy, j = (A.base / g.sy) % (uint32_t)g.n[1], k = A.base / g.sz;
+            const uint64_t colour = (uint64_t)((i & 1u) | ((j & 1u) << 1) | ((k & 1u) << 2));
+            R.key[slot] = (colour << (R.level_bits + R.cell_bits + R.pid_bits)) |
+                          ((uint64_t)A.level << (R.cell_bits + R.pid_bits)) | ((uint64_t)A.base << R.pid_bits) |
+                          (uint64_t)pid;
+            R.idx[slot] = slot;
+            float4* out = reinterpret_cast<float4*>(R.val + 24 * (size_t)slot);
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                out[q] = make_float4(A.v[(4 * q) / 3][(4 * q) % 3], A.v[(4 * q + 1) / 3][(4 * q + 1) % 3],
+                                     A.v[(4 * q + 2) / 3][(4 * q + 2) % 3], A.v[(4 * q + 3) / 3][(4 * q + 3) % 3]);
+            A.base = NO_CELL;
+            return;
+        }
+    }
     float* grid = in_global(gf[A.level]);
 #pragma unroll
     for (int c = 0; c < 2; ++c)
@@ -127,10 +156,10 @@ __device__ __forceinline__ void acc_flush(const Geom& g, float* const* gf, GradA
     A.base = NO_CELL;
 }
 
-__device__ __forceinline__ void acc_add(const Geom& g, float* const* gf, GradAcc& A, int level, uint32_t base,
-                                        const float f[3], float coef, const float lam[3]) {
+__device__ __forceinline__ void acc_add(const Geom& g, float* const* gf, const GradRec& R, uint32_t pid, GradAcc& A,
+                                        int level, uint32_t base, const float f[3], float coef, const float lam[3]) {
     if (A.base != base || A.level != level) {
-        acc_flush(g, gf, A);
+        acc_flush(g, gf, R, pid, A);
         A.base = base;
         A.level = level;
 #pragma unroll
@@ -243,22 +272,22 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a)
                     if (c == 0 && a.grad_f) {
                         if (MODE == MODE_FROZEN) {
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) acc_add(a.g, a.grad_f, acc, n, rec.base[s], rec.f[s], 1.f, lk[s]);
+                            for (int s = 0; s < 4; ++s) acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n, rec.base[s], rec.f[s], 1.f, lk[s]);
                         } else {
                             // level n+1 first (it already holds step n+1's share), then level n
-                            acc_add(a.g, a.grad_f, acc, n + 1, rec.base[1], rec.f[1], 0.5f, lk[1]);
-                            acc_add(a.g, a.grad_f, acc, n + 1, rec.base[2], rec.f[2], 0.5f, lk[2]);
-                            acc_add(a.g, a.grad_f, acc, n + 1, rec.base[3], rec.f[3], 1.f, lk[3]);
-                            acc_add(a.g, a.grad_f, acc, n, rec.base[0], rec.f[0], 1.f, lk[0]);
-                            acc_add(a.g, a.grad_f, acc, n, rec.base[1], rec.f[1], 0.5f, lk[1]);
-                            acc_add(a.g, a.grad_f, acc, n, rec.base[2], rec.f[2], 0.5f, lk[2]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n + 1, rec.base[1], rec.f[1], 0.5f, lk[1]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n + 1, rec.base[2], rec.f[2], 0.5f, lk[2]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n + 1, rec.base[3], rec.f[3], 1.f, lk[3]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n, rec.base[0], rec.f[0], 1.f, lk[0]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n, rec.base[1], rec.f[1], 0.5f, lk[1]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n, rec.base[2], rec.f[2], 0.5f, lk[2]);
                         }
                     }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) lam[c][d] += ly[0][d] + ly[1][d] + ly[2][d] + ly[3][d];
                 }
             }
-            if (a.grad_f) acc_flush(a.g, a.grad_f, acc);  // keep the accumulator out of the next recompute
+            if (a.grad_f) acc_flush(a.g, a.grad_f, a.grec, (uint32_t)p, acc);  // keep it out of the next recompute
         }
     }
 #pragma unroll
@@ -336,6 +365,16 @@ hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t
     case DT_F16: return launch_adj_d<DT_F16>(a, mode, s);
     default: return launch_adj_d<DT_BF16>(a, mode, s);
     }
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int n) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s) {

@@ -62,6 +62,10 @@ struct bto_ctx {
     int64_t ck_slots = 0;
     int ck_k = 0;                 // spacing recorded in this interval (0: nothing advected yet)
     bool ck_ok = false;           // every advect call since the seeding recorded, with spacing ck_k
+    // grid-gradient records of the adjoint (sorted reduction), grown on demand
+    void* grec_buf = nullptr;
+    size_t grec_bytes = 0;
+    bool grad_atomics = false;    // BTO_GRAD_ATOMICS=1: add grid gradients with FP32 atomics instead
     std::string err;
 };
 
@@ -141,6 +145,7 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     if (const char* e = std::getenv("BTO_MORTON_SEED")) c->morton_seed = std::atoi(e) != 0;
     if (const char* e = std::getenv("BTO_OCTANT_SEED")) c->octant_seed = std::atoi(e) != 0;
     if (const char* e = std::getenv("BTO_LANES_PER_PARTICLE")) c->lanes_per_particle = std::atoi(e) == 2 ? 2 : 1;
+    if (const char* e = std::getenv("BTO_GRAD_ATOMICS")) c->grad_atomics = std::atoi(e) != 0;
     if (const char* e = std::getenv("BTO_BRICK")) {
         int b0 = 0, b1 = 0, b2 = 0;
         if (std::sscanf(e, "%d,%d,%d", &b0, &b1, &b2) == 3 && b0 > 0 && b1 > 0 && b2 > 0 && b0 * b1 * b2 == 64) {
@@ -189,6 +194,7 @@ int bto_destroy(bto_ctx* c) {
     if (c->counts) (void)hipFree(c->counts);
     if (c->adj_scratch) (void)hipFree(c->adj_scratch);
     if (c->ck_rec) (void)hipFree(c->ck_rec);
+    if (c->grec_buf) (void)hipFree(c->grec_buf);
     if (c->rebin_buf) (void)hipFree(c->rebin_buf);
     if (c->rebin_temp) (void)hipFree(c->rebin_temp);
     delete c;
@@ -705,8 +711,74 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
         a.rec_meta = nullptr;
     }
     a.status_out = d_status;
+    // grid gradients: records for the sorted reduction, unless the key does not fit 64 bits
+    a.grec = GradRec{};
+    uint64_t* key_out = nullptr;
+    uint32_t* idx_out = nullptr;
+    void* sort_temp = nullptr;
+    size_t sort_bytes = 0;
+    if (d_grad_fields && !c->grad_atomics) {
+        auto bits_for = [](uint64_t v) {  // bits to hold 0 .. v
+            int b = 1;
+            while (b < 64 && (v >> b) != 0) ++b;
+            return b;
+        };
+        const uint64_t npts = (uint64_t)c->geom.n[0] * (uint64_t)c->geom.n[1] * (uint64_t)c->geom.n[2];
+        GradRec r{};
+        r.pid_bits = bits_for(P - 1);
+        r.cell_bits = bits_for(npts - 1);
+        r.level_bits = bits_for((uint64_t)n_steps);
+        const uint64_t per = 2 * sizeof(uint64_t) + 2 * sizeof(uint32_t) + 24 * sizeof(float);
+        uint64_t cap = (uint64_t)P * (uint64_t)(n_steps + 1) * 2 + 1024;
+        const uint64_t max_cap = ((uint64_t)1 << 30) / per * 4;  // at most ~4 GiB of records
+        if (cap > max_cap) cap = max_cap;
+        cap &= ~(uint64_t)15;  // keeps every array below 256-byte aligned
+        if (r.pid_bits + r.cell_bits + r.level_bits + 3 <= 64) {
+            r.cap = (uint32_t)cap;
+            sort_bytes = grad_sort_temp_bytes(r.cap, r.pid_bits + r.cell_bits + r.level_bits + 3);
+            const size_t temp_r = (sort_bytes + 255) & ~(size_t)255;
+            const size_t need_r = temp_r + (size_t)cap * per + 256;
+            if (need_r > c->grec_bytes) {
+                if (c->grec_buf) {
+                    e = hipStreamSynchronize(s);
+                    if (e != hipSuccess) return hip_fail(c, e, "gradient records sync");
+                    (void)hipFree(c->grec_buf);
+                    c->grec_buf = nullptr;
+                    c->grec_bytes = 0;
+                }
+                if (hipMalloc(&c->grec_buf, need_r) != hipSuccess) {
+                    (void)hipGetLastError();
+                    c->grec_buf = nullptr;
+                }
+                else c->grec_bytes = need_r;
+            }
+            if (c->grec_buf && sort_bytes > 0) {
+                // [sort temp | keys | sorted keys | indices | sorted indices | values | counter]
+                char* q = static_cast<char*>(c->grec_buf);
+                sort_temp = q;
+                r.key = reinterpret_cast<uint64_t*>(q + temp_r);
+                key_out = r.key + cap;
+                r.idx = reinterpret_cast<uint32_t*>(key_out + cap);
+                idx_out = r.idx + cap;
+                r.val = reinterpret_cast<float*>(idx_out + cap);
+                r.count = reinterpret_cast<uint32_t*>(r.val + 24 * (size_t)cap);
+                e = launch_zero_u32(r.count, 1, s);
+                if (e != hipSuccess) return hip_fail(c, e, "gradient record counter");
+                a.grec = r;
+            }
+        }
+    }
     e = launch_adjoint(a, dtype, mode, s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
+    if (a.grec.key) {
+        uint32_t n_rec = 0;
+        e = hipMemcpyAsync(&n_rec, a.grec.count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(c, e, "gradient record count");
+        if (n_rec > a.grec.cap) n_rec = a.grec.cap;  // the rest went to the grids with atomics
+        e = launch_grad_reduce(a.grec, n_rec, key_out, idx_out, sort_temp, sort_bytes, a.grad_f, c->geom, s);
+        if (e != hipSuccess) return hip_fail(c, e, "gradient reduction");
+    }
     return BTO_OK;
 }
 

@@ -88,6 +88,20 @@ struct FlowmapArgs {
     double* out_face;    // exit points (bto_exit_points)
 };
 
+// Grid-gradient records for the deterministic reduction: each accumulator
+// flush appends (key, 8 x 3 corner gradients) instead of adding them to the
+// grid with atomics; key = parity colour | level | cell | seed id (bit widths
+// below, colour on top).  key == null: atomics.  Flushes beyond cap fall back
+// to atomics.
+struct GradRec {
+    uint64_t* key;
+    uint32_t* idx;              // record index (the sort's values)
+    float* val;                 // cap x 24 floats
+    uint32_t* count;            // appended records (may exceed cap)
+    uint32_t cap;
+    int32_t pid_bits, cell_bits, level_bits;
+};
+
 struct AdjointArgs {
     const char* const* f;       // device array: N + 1 grids
     const double* h;            // device array: N step sizes
@@ -106,6 +120,7 @@ struct AdjointArgs {
     double* buf;                // k x P x 3 scratch (slot-major)
     uint8_t* status_out;        // P (may be null): status of the recomputed forward
     const int32_t* rec_meta;    // non-null: take the forward from recorded checkpoints and these records
+    GradRec grec;               // grid-gradient records (grec.key null: atomics)
 };
 
 // Checkpoint of the live particles for the adjoint: FP64 positions (cell
@@ -157,6 +172,12 @@ hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t 
 hipError_t launch_ckpt_store(const CkptArgs& a, int blocks_per_seg, hipStream_t s);
 int advect_max_blocks_per_cu(int dtype, int mode, int lanes_per_particle, int record_exit);
 hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
+size_t grad_sort_temp_bytes(uint32_t cap, int bits);
+// Sort the first n records by key and add each (level, cell) group's sum to the
+// grids, one parity colour at a time (no two cells of one colour share a corner).
+hipError_t launch_grad_reduce(const GradRec& r, uint32_t n, uint64_t* key_out, uint32_t* idx_out, void* temp,
+                              size_t temp_bytes, float* const* gf, const Geom& g, hipStream_t s);
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s);
 size_t rebin_temp_bytes(int64_t nbins_total);
 hipError_t launch_rebin(const RebinArgs& a, hipStream_t s);

@@ -343,3 +343,22 @@ def test_recorded_checkpoints_give_the_recomputed_gradients(shape):
         ga = np.concatenate([g.cpu().numpy().ravel() for g in gg_r])
         gb = np.concatenate([g.cpu().numpy().ravel() for g in gg_c])
         assert np.linalg.norm(ga - gb) / np.linalg.norm(gb) < 1e-5
+
+
+def test_grid_gradient_is_deterministic_and_matches_the_atomic_path(monkeypatch):
+    """The sorted reduction of the grid-gradient records gives bit-identical
+    grids on repeated calls, and the same values as adding every flush with
+    FP32 atomics (BTO_GRAD_ATOMICS=1) up to FP32 summation order."""
+    n, N, s, gr, seeds, w = _small()
+    _say("grid gradient: sorted reduction twice, then atomics")
+    _, st1, g1 = _gpu_adjoint(n, gr, s.times, seeds, w, ckpt=4, grid_grad=True)
+    _, st2, g2 = _gpu_adjoint(n, gr, s.times, seeds, w, ckpt=4, grid_grad=True)
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+    monkeypatch.setenv("BTO_GRAD_ATOMICS", "1")
+    _, st3, g3 = _gpu_adjoint(n, gr, s.times, seeds, w, ckpt=4, grid_grad=True)
+    assert np.array_equal(st1, st3)
+    ga = np.concatenate([g.ravel() for g in g1])
+    gb = np.concatenate([g.ravel() for g in g3])
+    assert np.abs(ga).max() > 0
+    assert np.abs(ga - gb).max() <= 1e-6 * np.abs(gb).max()
