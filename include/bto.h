@@ -214,11 +214,12 @@ int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
  *              d L / d V_c is ADDED to them.  Each particle's contributions
  *              to one cell of one grid are summed, recorded, sorted by
  *              (cell parity, grid, cell, seed) and added in that order, so
- *              the result is deterministic; the call synchronizes `stream`
- *              once more to size the sort.  Records beyond about 4 GiB (or
- *              with BTO_GRAD_ATOMICS=1 in the environment at context
- *              creation) are added with FP32 atomics instead, in no fixed
- *              order.  Only with n_cot = 1.
+ *              the result is deterministic.  A seed has room for
+ *              2 (n_steps + 1) + 2 records (fewer if all records would pass
+ *              about 4 GiB); its further ones, and all of them with
+ *              BTO_GRAD_ATOMICS=1 in the environment at context creation,
+ *              are added with FP32 atomics instead, in no fixed order.
+ *              Only with n_cot = 1.
  *   d_status (n_seeds bytes, may be NULL): BTO_VALID / BTO_TERMINATED /
  *              BTO_INVALID from the recomputed forward.
  * flags: BTO_TIME_LINEAR or BTO_TIME_FROZEN, optionally | BTO_RECORD_CKPT:

@@ -109,36 +109,29 @@ __device__ __forceinline__ void gT(const float G[3][3], const float v[3], float 
 struct GradAcc {
     uint32_t base;
     int level;
+    uint32_t nrec;  // records written by this seed
     float v[8][3];
 };
 
 __device__ __forceinline__ void acc_flush(const Geom& g, float* const* gf, const GradRec& R, uint32_t pid,
                                           GradAcc& A) {
     if (A.base == NO_CELL) return;
-    if (R.key) {
-        // one counter atomic per wavefront and flush round
-        const unsigned long long act = __ballot(1);
-        const int lane = (int)__lane_id();
-        const int leader = __ffsll((long long)act) - 1;
-        uint32_t first = 0;
-        if (lane == leader) first = atomicAdd(R.count, (uint32_t)__popcll(act));
-        first = __shfl(first, leader);
-        const uint32_t slot = first + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
-        if (slot < R.cap) {
-            const uint32_t i = A.base % g.sy, j = (A.base / g.sy) % (uint32_t)g.n[1], k = A.base / g.sz;
-            const uint64_t colour = (uint64_t)((i & 1u) | ((j & 1u) << 1) | ((k & 1u) << 2));
-            R.key[slot] = (colour << (R.level_bits + R.cell_bits + R.pid_bits)) |
-                          ((uint64_t)A.level << (R.cell_bits + R.pid_bits)) | ((uint64_t)A.base << R.pid_bits) |
-                          (uint64_t)pid;
-            R.idx[slot] = slot;
-            float4* out = reinterpret_cast<float4*>(R.val + 24 * (size_t)slot);
+    if (R.key && A.nrec < R.per_seed) {
+        // the seed's next record slot: no counter, and the lanes of a wavefront
+        // that flush together write neighbouring slots
+        const uint64_t slot = (uint64_t)(A.nrec++) * R.P + pid;
+        const uint32_t i = A.base % g.sy, j = (A.base / g.sy) % (uint32_t)g.n[1], k = A.base / g.sz;
+        const uint64_t colour = (uint64_t)((i & 1u) | ((j & 1u) << 1) | ((k & 1u) << 2));
+        R.key[slot] = (colour << (R.level_bits + R.cell_bits)) | ((uint64_t)A.level << R.cell_bits) |
+                      (uint64_t)A.base;
+        R.idx[slot] = (uint32_t)slot;
+        float4* out = reinterpret_cast<float4*>(R.val + 24 * (size_t)slot);
 #pragma unroll
-            for (int q = 0; q < 6; ++q)
-                out[q] = make_float4(A.v[(4 * q) / 3][(4 * q) % 3], A.v[(4 * q + 1) / 3][(4 * q + 1) % 3],
-                                     A.v[(4 * q + 2) / 3][(4 * q + 2) % 3], A.v[(4 * q + 3) / 3][(4 * q + 3) % 3]);
-            A.base = NO_CELL;
-            return;
-        }
+        for (int q = 0; q < 6; ++q)
+            out[q] = make_float4(A.v[(4 * q) / 3][(4 * q) % 3], A.v[(4 * q + 1) / 3][(4 * q + 1) % 3],
+                                 A.v[(4 * q + 2) / 3][(4 * q + 2) % 3], A.v[(4 * q + 3) / 3][(4 * q + 3) % 3]);
+        A.base = NO_CELL;
+        return;
     }
     float* grid = in_global(gf[A.level]);
 #pragma unroll
@@ -234,6 +227,7 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a)
     GradAcc acc;
     acc.base = NO_CELL;
     acc.level = -1;
+    acc.nrec = 0;
     if (status == S_VALID) {
         for (int sg = nseg - 1; sg >= 0; --sg) {
             const int n0 = sg * K;
@@ -365,16 +359,6 @@ hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t
     case DT_F16: return launch_adj_d<DT_F16>(a, mode, s);
     default: return launch_adj_d<DT_BF16>(a, mode, s);
     }
-}
-
-__global__ void zero_u32_kernel(uint32_t* p, int n) {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i < n) p[i] = 0u;
-}
-
-hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
-    hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, p, n);
-    return hipGetLastError();
 }
 
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s) {

@@ -711,12 +711,14 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
         a.rec_meta = nullptr;
     }
     a.status_out = d_status;
-    // grid gradients: records for the sorted reduction, unless the key does not fit 64 bits
+    // grid gradients: records for the sorted reduction, unless the key does not fit
     a.grec = GradRec{};
     uint64_t* key_out = nullptr;
     uint32_t* idx_out = nullptr;
+    uint32_t* bounds = nullptr;
     void* sort_temp = nullptr;
     size_t sort_bytes = 0;
+    uint64_t n_slots = 0;
     if (d_grad_fields && !c->grad_atomics) {
         auto bits_for = [](uint64_t v) {  // bits to hold 0 .. v
             int b = 1;
@@ -725,19 +727,21 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
         };
         const uint64_t npts = (uint64_t)c->geom.n[0] * (uint64_t)c->geom.n[1] * (uint64_t)c->geom.n[2];
         GradRec r{};
-        r.pid_bits = bits_for(P - 1);
+        r.P = (uint32_t)P;
         r.cell_bits = bits_for(npts - 1);
         r.level_bits = bits_for((uint64_t)n_steps);
+        const int kb = r.cell_bits + r.level_bits + 3;
         const uint64_t per = 2 * sizeof(uint64_t) + 2 * sizeof(uint32_t) + 24 * sizeof(float);
-        uint64_t cap = (uint64_t)P * (uint64_t)(n_steps + 1) * 2 + 1024;
-        const uint64_t max_cap = ((uint64_t)1 << 30) / per * 4;  // at most ~4 GiB of records
-        if (cap > max_cap) cap = max_cap;
-        cap &= ~(uint64_t)15;  // keeps every array below 256-byte aligned
-        if (r.pid_bits + r.cell_bits + r.level_bits + 3 <= 64) {
-            r.cap = (uint32_t)cap;
-            sort_bytes = grad_sort_temp_bytes(r.cap, r.pid_bits + r.cell_bits + r.level_bits + 3);
+        const uint64_t max_slots = ((uint64_t)4 << 30) / per;  // at most ~4 GiB of records
+        // about one flush per seed and level when particles keep their cells, plus cell changes
+        uint64_t ps = 2 * (uint64_t)(n_steps + 1) + 2;
+        if (ps * P > max_slots) ps = max_slots / P;
+        if (kb + 1 <= 64 && ps >= 1) {
+            r.per_seed = (uint32_t)ps;
+            n_slots = ((uint64_t)P * ps + 15) & ~(uint64_t)15;  // keeps every array 128-byte aligned
+            sort_bytes = grad_sort_temp_bytes(n_slots, kb + 1);
             const size_t temp_r = (sort_bytes + 255) & ~(size_t)255;
-            const size_t need_r = temp_r + (size_t)cap * per + 256;
+            const size_t need_r = temp_r + (size_t)n_slots * per + 256;
             if (need_r > c->grec_bytes) {
                 if (c->grec_buf) {
                     e = hipStreamSynchronize(s);
@@ -749,21 +753,22 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
                 if (hipMalloc(&c->grec_buf, need_r) != hipSuccess) {
                     (void)hipGetLastError();
                     c->grec_buf = nullptr;
+                } else {
+                    c->grec_bytes = need_r;
                 }
-                else c->grec_bytes = need_r;
             }
             if (c->grec_buf && sort_bytes > 0) {
-                // [sort temp | keys | sorted keys | indices | sorted indices | values | counter]
+                // [sort temp | keys | sorted keys | indices | sorted indices | values | colour bounds]
                 char* q = static_cast<char*>(c->grec_buf);
                 sort_temp = q;
                 r.key = reinterpret_cast<uint64_t*>(q + temp_r);
-                key_out = r.key + cap;
-                r.idx = reinterpret_cast<uint32_t*>(key_out + cap);
-                idx_out = r.idx + cap;
-                r.val = reinterpret_cast<float*>(idx_out + cap);
-                r.count = reinterpret_cast<uint32_t*>(r.val + 24 * (size_t)cap);
-                e = launch_zero_u32(r.count, 1, s);
-                if (e != hipSuccess) return hip_fail(c, e, "gradient record counter");
+                key_out = r.key + n_slots;
+                r.idx = reinterpret_cast<uint32_t*>(key_out + n_slots);
+                idx_out = r.idx + n_slots;
+                r.val = reinterpret_cast<float*>(idx_out + n_slots);
+                bounds = reinterpret_cast<uint32_t*>(r.val + 24 * (size_t)n_slots);
+                e = launch_grad_clear(r, n_slots, s);
+                if (e != hipSuccess) return hip_fail(c, e, "gradient record clear");
                 a.grec = r;
             }
         }
@@ -771,12 +776,7 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
     e = launch_adjoint(a, dtype, mode, s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint launch");
     if (a.grec.key) {
-        uint32_t n_rec = 0;
-        e = hipMemcpyAsync(&n_rec, a.grec.count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(c, e, "gradient record count");
-        if (n_rec > a.grec.cap) n_rec = a.grec.cap;  // the rest went to the grids with atomics
-        e = launch_grad_reduce(a.grec, n_rec, key_out, idx_out, sort_temp, sort_bytes, a.grad_f, c->geom, s);
+        e = launch_grad_reduce(a.grec, n_slots, key_out, idx_out, bounds, sort_temp, sort_bytes, a.grad_f, c->geom, s);
         if (e != hipSuccess) return hip_fail(c, e, "gradient reduction");
     }
     return BTO_OK;

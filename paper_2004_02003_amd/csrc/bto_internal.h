@@ -89,17 +89,20 @@ struct FlowmapArgs {
 };
 
 // Grid-gradient records for the deterministic reduction: each accumulator
-// flush appends (key, 8 x 3 corner gradients) instead of adding them to the
-// grid with atomics; key = parity colour | level | cell | seed id (bit widths
-// below, colour on top).  key == null: atomics.  Flushes beyond cap fall back
-// to atomics.
+// flush writes (key, 8 x 3 corner gradients) instead of adding them to the
+// grid with atomics; key = parity colour | level | cell (bit widths below,
+// colour on top; colour field 8 marks an unused slot).  The j-th flush of seed
+// p goes to slot j * P + p, a position fixed by (j, p) alone, so the stable
+// sort leaves each group's records in an order that does not depend on thread
+// timing.  A seed's flushes beyond per_seed fall back to atomics.  key == null:
+// atomics.
 struct GradRec {
     uint64_t* key;
     uint32_t* idx;              // record index (the sort's values)
-    float* val;                 // cap x 24 floats
-    uint32_t* count;            // appended records (may exceed cap)
-    uint32_t cap;
-    int32_t pid_bits, cell_bits, level_bits;
+    float* val;                 // per_seed * P x 24 floats
+    uint32_t per_seed;
+    uint32_t P;
+    int32_t cell_bits, level_bits;
 };
 
 struct AdjointArgs {
@@ -172,12 +175,13 @@ hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t 
 hipError_t launch_ckpt_store(const CkptArgs& a, int blocks_per_seg, hipStream_t s);
 int advect_max_blocks_per_cu(int dtype, int mode, int lanes_per_particle, int record_exit);
 hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);
-hipError_t launch_zero_u32(uint32_t* p, int n, hipStream_t s);
-size_t grad_sort_temp_bytes(uint32_t cap, int bits);
-// Sort the first n records by key and add each (level, cell) group's sum to the
+size_t grad_sort_temp_bytes(uint64_t n, int bits);
+// Mark all n record slots unused (before the adjoint sweep writes them).
+hipError_t launch_grad_clear(const GradRec& r, uint64_t n, hipStream_t s);
+// Sort the n record slots by key and add each (level, cell) group's sum to the
 // grids, one parity colour at a time (no two cells of one colour share a corner).
-hipError_t launch_grad_reduce(const GradRec& r, uint32_t n, uint64_t* key_out, uint32_t* idx_out, void* temp,
-                              size_t temp_bytes, float* const* gf, const Geom& g, hipStream_t s);
+hipError_t launch_grad_reduce(const GradRec& r, uint64_t n, uint64_t* key_out, uint32_t* idx_out, uint32_t* bounds,
+                              void* temp, size_t temp_bytes, float* const* gf, const Geom& g, hipStream_t s);
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s);
 size_t rebin_temp_bytes(int64_t nbins_total);
 hipError_t launch_rebin(const RebinArgs& a, hipStream_t s);

@@ -1,11 +1,12 @@
 // Deterministic reduction of the adjoint's grid-gradient records.
 //
-// The reverse sweep appends one record per accumulator flush: the 8 corner
-// gradients (x 3 components) of one cell of one grid level, keyed by
-// parity colour | level | cell | seed id.  A stable radix sort orders the
-// records by key; then, one colour at a time, each (level, cell) group is
-// summed in key order (by seed id, then flush order) and added to the grid's
-// 8 corners with plain loads and stores.  Two different cells of one colour
+// The reverse sweep writes one record per accumulator flush into its seed's
+// own slots: the 8 corner gradients (x 3 components) of one cell of one grid
+// level, keyed by parity colour | level | cell (unused slots carry a key above
+// every colour).  A stable radix sort orders the records by key; then, one
+// colour at a time (a contiguous range of the sorted keys), each (level,
+// cell) group is summed in slot order (the flush's rank, then the seed id)
+// and added to the grid's 8 corners with plain loads and stores.  Two different cells of one colour
 // differ by at least two cells along some axis, so their corner sets are
 // disjoint and the stores of one colour never collide; the colours are
 // applied in a fixed order.  The result does not depend on thread timing,
@@ -17,21 +18,35 @@
 
 namespace bto {
 
+__global__ __launch_bounds__(BLOCK) void grad_clear_kernel(uint64_t* key, uint64_t n, uint64_t empty) {
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (uint64_t)gridDim.x * BLOCK)
+        key[i] = empty;
+}
+
+// bounds[c] = first sorted slot of colour c (c = 0..8; colour 8 = unused slots).
+__global__ __launch_bounds__(BLOCK) void grad_bounds_kernel(const uint64_t* key, uint64_t n, int colour_shift,
+                                                            uint32_t* bounds) {
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i <= n; i += (uint64_t)gridDim.x * BLOCK) {
+        const uint64_t c = i < n ? (key[i] >> colour_shift) : 9;
+        const uint64_t cp = i > 0 ? (key[i - 1] >> colour_shift) : 0;
+        const uint64_t lo = i > 0 ? cp + 1 : 0;
+        for (uint64_t q = lo; q <= c && q <= 8; ++q) bounds[q] = (uint32_t)i;
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void grad_apply_kernel(const uint64_t* key, const uint32_t* idx, const float* val,
-                                                           uint32_t n, uint64_t colour, int colour_shift,
-                                                           int pid_bits, uint64_t cell_mask, int level_shift,
-                                                           uint64_t level_mask, float* const* gf, Geom g) {
-    // a group is one (colour, level, cell): the key without its seed-id bits
-    const int group_shift = pid_bits;
-    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+                                                           const uint32_t* bounds, int colour, uint64_t cell_mask,
+                                                           int level_shift, uint64_t level_mask, float* const* gf,
+                                                           Geom g) {
+    // a group is one (colour, level, cell): a run of equal keys
+    const uint32_t lo = bounds[colour], hi = bounds[colour + 1];
+    for (uint32_t i = lo + blockIdx.x * BLOCK + threadIdx.x; i < hi; i += gridDim.x * BLOCK) {
         const uint64_t k = key[i];
-        if ((k >> colour_shift) != colour) continue;
-        const uint64_t group = k >> group_shift;
-        if (i > 0 && (key[i - 1] >> group_shift) == group) continue;  // not the first record of its group
+        if (i > lo && key[i - 1] == k) continue;  // not the first record of its group
         float s[24];
 #pragma unroll
         for (int q = 0; q < 24; ++q) s[q] = 0.f;
-        for (uint32_t j = i; j < n && (key[j] >> group_shift) == group; ++j) {
+        for (uint32_t j = i; j < hi && key[j] == k; ++j) {
             const float4* v = reinterpret_cast<const float4*>(val + 24 * (size_t)idx[j]);
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
@@ -42,7 +57,7 @@ __global__ __launch_bounds__(BLOCK) void grad_apply_kernel(const uint64_t* key, 
                 s[4 * q + 3] += x.w;
             }
         }
-        const uint32_t base = (uint32_t)((k >> pid_bits) & cell_mask);
+        const uint32_t base = (uint32_t)(k & cell_mask);
         const int level = (int)((k >> level_shift) & level_mask);
         float* grid = gf[level];
 #pragma unroll
@@ -60,29 +75,45 @@ __global__ __launch_bounds__(BLOCK) void grad_apply_kernel(const uint64_t* key, 
     }
 }
 
-size_t grad_sort_temp_bytes(uint32_t cap, int bits) {
+static int key_bits(const GradRec& r) { return r.level_bits + r.cell_bits + 3; }
+
+size_t grad_sort_temp_bytes(uint64_t n, int bits) {
     size_t bytes = 0;
     if (rocprim::radix_sort_pairs(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint32_t*)nullptr,
-                                  (uint32_t*)nullptr, (size_t)cap, 0u, (unsigned)bits) != hipSuccess)
+                                  (uint32_t*)nullptr, (size_t)n, 0u, (unsigned)bits) != hipSuccess)
         return 0;
     return bytes;
 }
 
-hipError_t launch_grad_reduce(const GradRec& r, uint32_t n, uint64_t* key_out, uint32_t* idx_out, void* temp,
-                              size_t temp_bytes, float* const* gf, const Geom& g, hipStream_t s) {
+static unsigned grid_of(uint64_t n) {
+    const uint64_t b = (n + BLOCK - 1) / BLOCK;
+    return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+hipError_t launch_grad_clear(const GradRec& r, uint64_t n, hipStream_t s) {
+    // unused slots: the colour field reads 8, above every real colour
+    const uint64_t empty = (uint64_t)8 << (key_bits(r) - 3);
+    hipLaunchKernelGGL(grad_clear_kernel, dim3(grid_of(n)), dim3(BLOCK), 0, s, r.key, n, empty);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const GradRec& r, uint64_t n, uint64_t* key_out, uint32_t* idx_out, uint32_t* bounds,
+                              void* temp, size_t temp_bytes, float* const* gf, const Geom& g, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    const int colour_shift = r.level_bits + r.cell_bits + r.pid_bits;
-    const int bits = colour_shift + 3;
+    const int colour_shift = key_bits(r) - 3;
     size_t bytes = temp_bytes;
+    // one more bit than the key fields: the unused-slot marker
     hipError_t e = rocprim::radix_sort_pairs(temp, bytes, r.key, key_out, r.idx, idx_out, (size_t)n, 0u,
-                                             (unsigned)bits, s);
+                                             (unsigned)(key_bits(r) + 1), s);
     if (e != hipSuccess) return e;
-    const uint64_t cell_mask = (r.cell_bits >= 64) ? ~0ull : ((1ull << r.cell_bits) - 1ull);
+    hipLaunchKernelGGL(grad_bounds_kernel, dim3(grid_of(n + 1)), dim3(BLOCK), 0, s, key_out, n, colour_shift, bounds);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint64_t cell_mask = (1ull << r.cell_bits) - 1ull;
     const uint64_t level_mask = (1ull << r.level_bits) - 1ull;
-    const unsigned blocks = (unsigned)((n + BLOCK - 1) / BLOCK);
-    for (uint64_t colour = 0; colour < 8; ++colour) {
-        hipLaunchKernelGGL(grad_apply_kernel, dim3(blocks), dim3(BLOCK), 0, s, key_out, idx_out, r.val, n, colour,
-                           colour_shift, r.pid_bits, cell_mask, r.cell_bits + r.pid_bits, level_mask, gf, g);
+    for (int colour = 0; colour < 8; ++colour) {
+        hipLaunchKernelGGL(grad_apply_kernel, dim3(grid_of(n / 8 + 1)), dim3(BLOCK), 0, s, key_out, idx_out, r.val,
+                           bounds, colour, cell_mask, r.cell_bits, level_mask, gf, g);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
