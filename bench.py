@@ -40,6 +40,26 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def device_copy_rate(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """GB/s (read + write bytes) of a plain device-to-device copy, median of reps."""
+    import torch
+
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (float(np.median(ts)) * 1e-3) / 1e9
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -577,6 +597,11 @@ def main(argv=None):
             "kernel": f"advect_kernel<{dt},linear>", "launches_per_step": len(plan),
             "avg_launch_ms": round(launch_ms, 4),
             "algorithmic_bytes_per_launch": int(bytes_interval / len(plan))}
+    # context for the peak: what a plain 1 GiB device-to-device copy reaches on this GPU
+    copy_gbs = device_copy_rate()
+    roof["device_copy_GBs"] = round(copy_gbs, 1)
+    if traffic:
+        roof["traffic_GBs"] = round(traffic / (launch_ms * 1e-3) / 1e9, 1)
     log(f"{value:.3e} particle-steps/s, {ms_per_step:.3f} ms per interval, advect {adv_ms:.3f} ms, "
         f"{achieved:.0f} GB/s algorithmic")
 
