@@ -18,7 +18,7 @@ from typing import Callable, List, Optional
 
 import torch
 
-from .context import Context
+from .context import _TORCH_DT, Context
 
 
 class InSituDriver:
@@ -102,18 +102,29 @@ class InSituDriver:
         self.steps_in_interval = 0
         self._t0 = t
 
+    def _check_grid(self, g: torch.Tensor):
+        # each grid is checked once, when it arrives; the step then passes raw pointers
+        shape = (self.ctx.n[2], self.ctx.n[1], self.ctx.n[0], 3)
+        if g.dtype not in _TORCH_DT or tuple(g.shape) != shape or not g.is_contiguous() or not g.is_cuda:
+            raise ValueError(f"every grid must be a contiguous float32/float16/bfloat16 device tensor of shape {shape}")
+        if self._prev is not None and g.dtype != self._prev.dtype:
+            raise ValueError("all grids of a run must share one dtype")
+
     def cycle(self, grid: torch.Tensor, t: float):
         """Consume the grid of the next cycle at time ``t``."""
+        self._check_grid(grid)
         g, k = self._own(grid)
         if self._prev is None:
             self._start_interval(t)
         else:
             cs = self._compute or torch.cuda.current_stream()
+            ptrs = (self._prev.data_ptr(), g.data_ptr())
+            times = (self._prev_t, float(t))
             if self.timing:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(cs)
-            self.ctx.advect([self._prev, g], [self._prev_t, t], mode=self.mode, stream=self._compute)
+            self.ctx.advect_ptrs(ptrs, times, _TORCH_DT[g.dtype], mode=self.mode, stream=cs)
             if self.timing:
                 e1.record(cs)
                 self._events.append((e0, e1))
