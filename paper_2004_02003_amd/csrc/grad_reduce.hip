@@ -1,17 +1,18 @@
 // Deterministic reduction of the adjoint's grid-gradient records.
 //
-// The reverse sweep writes one record per accumulator flush into its seed's
-// own slots: the 8 corner gradients (x 3 components) of one cell of one grid
-// level, keyed by parity colour | level | cell (unused slots carry a key above
-// every colour).  A stable radix sort orders the records by key; then, one
-// colour at a time (a contiguous range of the sorted keys), each (level,
-// cell) group is summed in slot order (the flush's rank, then the seed id)
-// and added to the grid's 8 corners with plain loads and stores.  Two different cells of one colour
-// differ by at least two cells along some axis, so their corner sets are
-// disjoint and the stores of one colour never collide; the colours are
-// applied in a fixed order.  The result does not depend on thread timing,
-// unlike FP32 atomics, and each corner costs one read and one write per
-// group instead of one memory-side atomic per contribution.
+// The reverse sweep writes one record per accumulator flush into a slot fixed
+// by (flush rank, seed): the 8 corner gradients (x 3 components) of one cell
+// of one grid level, keyed by parity colour | level | cell (unused slots carry
+// a key above every colour).  A stable radix sort orders the records by key;
+// then, one colour at a time (a contiguous range of the sorted keys), each
+// (level, cell) group is summed in slot order (the flush's rank, then the
+// seed id) and added to the grid's 8 corners with plain loads and stores.
+// Two different cells of one colour differ by at least two cells along some
+// axis, so their corner sets are disjoint and the stores of one colour never
+// collide; the colours are applied in a fixed order.  The result does not
+// depend on thread timing, unlike FP32 atomics, and each corner costs one
+// read and one write per group instead of one memory-side atomic per
+// contribution.
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "bto_internal.h"
