@@ -538,3 +538,36 @@ def test_randomized_small_blocks_against_the_oracle():
                            mode=oracle.FROZEN if mode == "frozen" else oracle.LINEAR)
         compare(g, o, label=f"random case {case}")
         assert g["n_valid"] == int((g["flag"] == 0).sum())
+
+
+def test_largest_block_axis_closed_form_and_oracle():
+    """A block at the largest supported axis length (1,024 points, the 10-bit
+    cell index of the packed particle state) in uniform flow along x: seeds
+    across the whole axis, including the last cells, end at x0 + u t or
+    terminate in the step that would cross the x = 1023 face, as the closed
+    form and the oracle say (also with a lattice seeded over the full axis)."""
+    n = (1024, 4, 3)
+    N = 8
+    times = np.arange(N + 1) * 0.25
+    u = (3.7, 0.1, 0.0)
+    s = fields.uniform_flow(n, u, times)
+    gr = s.grids("f32")
+    xs = np.array([0.3, 500.5, 1000.0, 1015.2, 1016.9, 1019.0, 1021.7, 1022.99, 1023.0])
+    seeds = np.stack([xs, np.full_like(xs, 1.5), np.full_like(xs, 1.0)], axis=1)
+    _say("largest block axis 1024")
+    dev = _dev(gr, "f32")
+    g = run_gpu(n, dev, times, seeds=seeds, record_exit=True)
+    o = oracle.flowmap(oracle.Field(n, gr), times, seeds, N)
+    compare(g, o, label="axis 1024")
+    # closed form: x(t) = x0 + u t while inside
+    ux = np.float32(3.7)
+    for i, x0 in enumerate(xs):
+        ends = x0 + float(ux) * (times[1:] - times[0])
+        inside = ends <= 1023.0
+        e = N if inside.all() else int(np.argmin(inside))
+        assert g["exit"][i] == e, (x0, g["exit"][i], e)
+        want = x0 + float(ux) * (times[e] - times[0])
+        assert abs(g["end"][i, 0] - want) < 1e-5
+    gl = run_gpu(n, dev, times, stride=3)
+    _, ol = oracle_lattice(oracle.Field(n, gr), times, n, 3, N)
+    compare(gl, ol, label="axis 1024 lattice")

@@ -52,7 +52,7 @@ def test_create_rejects_bad_blocks_before_touching_a_device(lib):
     from paper_2004_02003_amd import _lib
 
     h = ctypes.c_void_p()
-    for n, sp, cap in [((1, 8, 8), 1.0, 10), ((8, 8, 2000), 1.0, 10), ((8, 8, 8), 0.0, 10),
+    for n, sp, cap in [((1, 8, 8), 1.0, 10), ((8, 8, 2000), 1.0, 10), ((8, 1025, 8), 1.0, 10), ((8, 8, 8), 0.0, 10),
                        ((8, 8, 8), float("nan"), 10), ((8, 8, 8), 1.0, 0)]:
         blk = _lib.Block()
         blk.n[:] = n
