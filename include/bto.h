@@ -210,7 +210,8 @@ int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
  *              Jacobian dx_end/dx_0 per seed, row-major).
  *   d_grad_seed (n_seeds x n_cot x 3 floats): d L / d x_0 per cotangent.
  *   d_grad_fields: NULL, or a HOST array of n_steps + 1 device pointers to
- *              distinct float32 grids shaped like the velocity grids;
+ *              float32 grids shaped like the velocity grids (non-overlapping;
+ *              if one pointer repeats, the atomic path below is used);
  *              d L / d V_c is ADDED to them.  Each particle's contributions
  *              to one cell of one grid are summed, recorded, sorted by
  *              (cell parity, grid, cell, seed) and added in that order, so

@@ -3,6 +3,7 @@
 // (and adjoint.hip); this file only owns memory and enqueues work.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -719,7 +720,13 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
     void* sort_temp = nullptr;
     size_t sort_bytes = 0;
     uint64_t n_slots = 0;
-    if (d_grad_fields && !c->grad_atomics) {
+    bool grads_distinct = true;  // the colour passes store without atomics: one buffer per grid
+    if (d_grad_fields) {
+        std::vector<const void*> gp(d_grad_fields, d_grad_fields + n_steps + 1);
+        std::sort(gp.begin(), gp.end());
+        grads_distinct = std::adjacent_find(gp.begin(), gp.end()) == gp.end();
+    }
+    if (d_grad_fields && !c->grad_atomics && grads_distinct) {
         auto bits_for = [](uint64_t v) {  // bits to hold 0 .. v
             int b = 1;
             while (b < 64 && (v >> b) != 0) ++b;

@@ -389,3 +389,27 @@ def test_grid_gradient_when_records_overflow_into_atomics(monkeypatch):
     go, ggo = oracle.adjoint(oracle.Field((n, n, n), gr), s.times, seeds, N, w, grid_grad=True)
     C = np.concatenate([g.ravel() for g in ggo])
     assert np.linalg.norm(A - C) / np.linalg.norm(C) < 1e-3
+
+
+def test_grid_gradient_with_one_buffer_for_every_grid():
+    """When every grid's gradient is the same buffer the library uses the
+    atomic path, and the buffer receives the sum over all levels."""
+    import torch
+    from paper_2004_02003_amd import Context
+
+    n, N, s, gr, seeds, w = _small()
+    dev = _dev(gr)
+    cot = torch.as_tensor(w, dtype=torch.float32, device="cuda").contiguous()
+    _say("grid gradient into one shared buffer")
+    with Context(n, len(seeds)) as ctx:
+        x0 = torch.as_tensor(seeds, dtype=torch.float64, device="cuda")
+        ctx.seed_explicit(x0)
+        gg = [torch.zeros_like(g) for g in dev]
+        ctx.adjoint(dev, s.times, cot, grad_grids=gg, ckpt_every=4)
+        ctx.seed_explicit(x0)
+        one = torch.zeros_like(dev[0])
+        ctx.adjoint(dev, s.times, cot, grad_grids=[one] * len(dev), ckpt_every=4)
+        torch.cuda.synchronize()
+        total = torch.stack(gg).sum(0).cpu().numpy()
+        got = one.cpu().numpy()
+    assert np.abs(got - total).max() <= 1e-5 * np.abs(total).max()
