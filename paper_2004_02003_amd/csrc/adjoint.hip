@@ -78,19 +78,6 @@ __device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const
     return S_VALID;
 }
 
-// Pointers read from a device array (the grid tables) are generic to the
-// compiler, which then emits flat memory instructions for every gather and
-// atomic through them; flat instructions also count against the scalar-load
-// counter, so their waits and those of scalar loads merge.  Every grid lives in
-// global memory: rebuilding the pointer in the global address space (through
-// its integer value, which no pass folds back into the generic pointer) lets
-// the compiler emit the global forms.
-template <class T>
-__device__ __forceinline__ T* in_global(T* p) {
-    using G = __attribute__((address_space(1))) T*;
-    return (T*)(G)(uintptr_t)p;
-}
-
 __device__ __forceinline__ void gT(const float G[3][3], const float v[3], float out[3]) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) out[d] = G[0][d] * v[0] + G[1][d] * v[1] + G[2][d] * v[2];

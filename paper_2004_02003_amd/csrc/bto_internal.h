@@ -12,6 +12,19 @@ namespace bto {
 // buffers.  Workgroup b of a launch works on segment b % NSEG: consecutive
 // workgroups are dispatched round-robin over the 8 XCDs, so each XCD keeps
 // one spatially compact slab of particles (and of the field) in its own L2.
+// Pointers read from a device array (the grid tables) are generic to the
+// compiler, which then emits flat memory instructions for every gather and
+// atomic through them; flat instructions also count against the scalar-load
+// counter, so their waits and those of scalar loads merge.  Every grid lives in
+// global memory: rebuilding the pointer in the global address space (through
+// its integer value, which no pass folds back into the generic pointer) lets
+// the compiler emit the global forms.
+template <class T>
+__device__ __forceinline__ T* in_global(T* p) {
+    using G = __attribute__((address_space(1))) T*;
+    return (T*)(G)(uintptr_t)p;
+}
+
 struct Segs {
     int64_t base[NSEG];  // first slot of each segment
 };

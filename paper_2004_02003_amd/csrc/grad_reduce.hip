@@ -60,7 +60,7 @@ __global__ __launch_bounds__(BLOCK) void grad_apply_kernel(const uint64_t* key, 
         }
         const uint32_t base = (uint32_t)(k & cell_mask);
         const int level = (int)((k >> level_shift) & level_mask);
-        float* grid = gf[level];
+        float* grid = in_global(gf[level]);
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
