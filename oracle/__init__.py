@@ -196,6 +196,20 @@ def adjoint(field: Field, times, seeds: np.ndarray, n_steps: int, cot: np.ndarra
     return (g, gg) if grid_grad else g
 
 
+def fetch(field: Field, c: int, ijk) -> np.ndarray:
+    """The stored values of grid points ``ijk`` (M x 3 integer indices) of
+    cycle ``c`` as the oracle reads them (through the field's fetch callback,
+    before any interpolation)."""
+    fn = FETCH_FN(field.fn)
+    ijk = np.asarray(ijk, dtype=np.int64).reshape(-1, 3)
+    out = np.empty((len(ijk), 3))
+    buf = (ctypes.c_double * 3)()
+    for q, (i, j, k) in enumerate(ijk):
+        fn(field.user, int(c), int(i), int(j), int(k), buf)
+        out[q] = buf[:]
+    return out
+
+
 def sample(field: Field, times, n: int, theta: float, p, mode: int = LINEAR):
     """Velocity S(p, n, theta) and its spatial gradient (3x3) at one point."""
     pr, tkeep = _problem(field, times, max(n + 1, 1), mode, 0)

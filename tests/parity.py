@@ -54,10 +54,24 @@ def run_gpu(n, grids_dev, times, stride=None, seeds=None, mode="linear", chunks=
         ctx.close()
 
 
-def compare(g, o, pos_tol=POS_TOL, margin=MARGIN, per_particle_tol=None, label=""):
-    """Assert parity of a GPU flow map ``g`` with an oracle result ``o``."""
+# At most this fraction of the particles may be set aside as ties (oracle
+# margin below MARGIN) before a comparison counts as failed: a face margin that
+# came out too small would otherwise exclude everything and pass vacuously.
+MAX_EXCLUDED = 0.01
+
+
+def compare(g, o, pos_tol=POS_TOL, margin=MARGIN, per_particle_tol=None, label="", max_excluded=MAX_EXCLUDED):
+    """Assert parity of a GPU flow map ``g`` with an oracle result ``o``.
+
+    Particles whose oracle decision points come within ``margin`` of a face
+    are left out of the flag / exit-step / position checks; their fraction
+    must stay at or below ``max_excluded`` (tests that put seeds on faces on
+    purpose pass that fraction plus the usual allowance)."""
     amb = o["margin"] < margin
     ok = ~amb
+    excluded = float(amb.mean()) if amb.size else 0.0
+    assert amb.size == 0 or ok.sum() > 0, f"{label}: every particle excluded as a tie"
+    assert excluded <= max_excluded, f"{label}: {excluded:.2%} of the particles excluded as ties (> {max_excluded:.2%})"
     bad_flag = np.nonzero(ok & (g["flag"] != o["flag"]))[0]
     assert bad_flag.size == 0, f"{label}: flag mismatch at {bad_flag[:10]} (of {ok.sum()})"
     bad_exit = np.nonzero(ok & (g["exit"] != o["exit"]))[0]
@@ -67,7 +81,7 @@ def compare(g, o, pos_tol=POS_TOL, margin=MARGIN, per_particle_tol=None, label="
     bad = np.nonzero(ok & (err > tol))[0]
     assert bad.size == 0, (f"{label}: end position error {err[bad[:5]]} > tol at {bad[:5]}; "
                            f"max err {err[ok].max():.3e}")
-    res = dict(n=len(err), ambiguous=int(amb.sum()), max_err=float(err[ok].max()) if ok.any() else 0.0,
+    res = dict(n=len(err), ambiguous=int(amb.sum()), excluded_frac=excluded, max_err=float(err[ok].max()) if ok.any() else 0.0,
                mean_err=float(err[ok].mean()) if ok.any() else 0.0,
                terminated=float((o["flag"] == oracle.TERMINATED).mean()))
     if "face" in g and "face" in o:

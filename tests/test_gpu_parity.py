@@ -536,7 +536,9 @@ def test_randomized_small_blocks_against_the_oracle():
                     record_exit=(case % 2 == 0))
         o = oracle.flowmap(oracle.Field(n, gr, dtype=dt), times, seeds, N,
                            mode=oracle.FROZEN if mode == "frozen" else oracle.LINEAR)
-        compare(g, o, label=f"random case {case}")
+        on_face = np.any((seeds == 0.0) | (seeds == hi), axis=1)
+        assert np.all(o["margin"][on_face] == 0.0)
+        compare(g, o, label=f"random case {case}", max_excluded=float(on_face.mean()) + 0.01)
         assert g["n_valid"] == int((g["flag"] == 0).sum())
 
 
@@ -558,7 +560,8 @@ def test_largest_block_axis_closed_form_and_oracle():
     dev = _dev(gr, "f32")
     g = run_gpu(n, dev, times, seeds=seeds, record_exit=True)
     o = oracle.flowmap(oracle.Field(n, gr), times, seeds, N)
-    compare(g, o, label="axis 1024")
+    # one of the nine seeds starts on the x = 1023 face (margin 0)
+    compare(g, o, label="axis 1024", max_excluded=1.0 / len(xs))
     # closed form: x(t) = x0 + u t while inside
     ux = np.float32(3.7)
     for i, x0 in enumerate(xs):
