@@ -278,6 +278,20 @@ int bto_reconstruct_lattice(const int32_t m[3], double *d_end_xyz, const uint8_t
 int bto_flowmap_error(int64_t n, const double *d_b_xyz, const uint8_t *d_b_state, const double *d_m_xyz,
                       const uint8_t *d_m_flag, double cell, double *out5, void *stream);
 
+/* bto_flowmap_error without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and errors as bto_flowmap_error,
+ * bit-identical to it; its partial sums live in a fixed device array of
+ * 1,025 records (32,800 bytes) that the library keeps on each GPU it runs on
+ * until the process ends, enough for every n (BTO_ERANGE would report an n
+ * whose partials did not fit).  Every call on one GPU shares that array and
+ * finds it as the previous call left it (each call writes every record it
+ * reads, so nothing needs clearing): calls that overlap on one GPU, from
+ * several host threads or on several streams, race and must be serialized by
+ * the caller.  out5 is host memory; synchronizes `stream`. */
+int bto_flowmap_error_static(int64_t n, const double *d_b_xyz, const uint8_t *d_b_state, const double *d_m_xyz,
+                             const uint8_t *d_m_flag, double cell, double *out5, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

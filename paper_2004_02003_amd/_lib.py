@@ -25,7 +25,7 @@ EXPORTED = [
     "bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
     "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle",
     "bto_set_tuning", "bto_get_tuning", "bto_exit_points", "bto_place_block", "bto_reconstruct_lattice",
-    "bto_flowmap_error",
+    "bto_flowmap_error", "bto_flowmap_error_static",
 ]
 
 _ERRNAMES = {BTO_EINVAL: "BTO_EINVAL", BTO_ENOMEM: "BTO_ENOMEM", BTO_EHIP: "BTO_EHIP",
@@ -82,6 +82,7 @@ def load() -> ctypes.CDLL:
     L.bto_reconstruct_lattice.argtypes = [i32p, vp, vp, vp, vp]
     L.bto_flowmap_error.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_double,
                                     ctypes.POINTER(ctypes.c_double), vp]
+    L.bto_flowmap_error_static.argtypes = L.bto_flowmap_error.argtypes
     L.bto_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
     L.bto_adjoint_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
     L.bto_ftle.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]

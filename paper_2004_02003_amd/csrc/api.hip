@@ -581,6 +581,25 @@ int bto_flowmap_error(int64_t n, const double* d_b_xyz, const uint8_t* d_b_state
     return BTO_OK;
 }
 
+int bto_flowmap_error_static(int64_t n, const double* d_b_xyz, const uint8_t* d_b_state, const double* d_m_xyz,
+                             const uint8_t* d_m_flag, double cell, double* out5, void* stream) {
+    if (n < 1 || !d_b_xyz || !d_b_state || !d_m_xyz || !d_m_flag || !out5 || !(cell > 0.0)) return BTO_EINVAL;
+    void* scratch = nullptr;
+    size_t have = 0;
+    if (err_static_scratch(&scratch, &have) != hipSuccess) return BTO_EHIP;
+    if (err_scratch_bytes(n) > have) return BTO_ERANGE;
+    double r[4];
+    if (launch_flowmap_error(n, d_b_xyz, d_b_state, d_m_xyz, d_m_flag, scratch, r, (hipStream_t)stream) != hipSuccess)
+        return BTO_EHIP;
+    const double mean = r[2] > 0 ? r[0] / r[2] : 0.0;
+    out5[0] = mean;
+    out5[1] = r[1];
+    out5[2] = r[2];
+    out5[3] = r[3];
+    out5[4] = (cell - mean) / cell * 100.0;
+    return BTO_OK;
+}
+
 int bto_place_block(const int32_t mb[3], const int32_t M[3], const int32_t off[3], const double shift3[3],
                     const double* d_src_xyz, const uint8_t* d_src_flag, double* d_dst_xyz, uint8_t* d_dst_flag,
                     void* stream) {

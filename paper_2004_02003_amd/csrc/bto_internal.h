@@ -181,6 +181,9 @@ hipError_t launch_reconstruct(const int32_t m[3], double* end, const uint8_t* fl
 size_t err_scratch_bytes(int64_t P);
 hipError_t launch_flowmap_error(int64_t P, const double* b, const uint8_t* bstate, const double* m, const uint8_t* mflag,
                                 void* scratch, double out4[4], hipStream_t s);
+// This GPU's copy of the fixed scratch of the allocation-free metric (looked
+// up on the first call on each device) and its size in bytes.
+hipError_t err_static_scratch(void** ptr, size_t* bytes);
 hipError_t launch_place(const int32_t mb[3], const int32_t M[3], const int32_t off[3], const double shift[3],
                         const double* src_xyz, const uint8_t* src_flag, double* dst_xyz, uint8_t* dst_flag,
                         hipStream_t s);

@@ -10,6 +10,8 @@
 // wavefront, which fills every run of unknown entries that has known entries
 // on both sides.  Lines of one pass are disjoint, so a pass needs no
 // synchronisation beyond the kernel boundary.
+#include <mutex>
+
 #include "bto_internal.h"
 
 namespace bto {
@@ -236,6 +238,36 @@ hipError_t launch_flowmap_error(int64_t P, const double* b, const uint8_t* bstat
     out4[1] = r.max;
     out4[2] = (double)r.n;
     out4[3] = (double)r.uncovered;
+    return hipSuccess;
+}
+
+// Fixed device scratch of the allocation-free accuracy metric: room for the
+// largest partial-sum grid (1,024 workgroups) plus the final record, which
+// covers every entry count.  Each GPU holds its own copy at its own address,
+// found once per device with hipGetSymbolAddress; host code uses only that
+// address (the array's name on the host is a stand-in, not device memory).
+// Every call on one GPU shares the array: calls that overlap on one GPU race.
+constexpr size_t ERR_STATIC_BYTES = 1025 * sizeof(ErrPart);
+static __device__ __align__(256) char scratch[ERR_STATIC_BYTES];
+constexpr int ERR_STATIC_MAX_DEVICES = 64;
+
+hipError_t err_static_scratch(void** ptr, size_t* bytes) {
+    static std::mutex mu;
+    static void* addr[ERR_STATIC_MAX_DEVICES] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= ERR_STATIC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = ERR_STATIC_BYTES;
     return hipSuccess;
 }
 
