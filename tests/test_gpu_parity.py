@@ -70,7 +70,7 @@ def test_uniform_flow_closed_form_on_gpu():
     s = fields.uniform_flow(n, u, times)
     g = run_gpu(n, _dev(s.grids("f32"), "f32"), times, stride=3, record_exit=True)
     o = oracle.flowmap(oracle.Field(n, s.grids("f32")), times, oracle.seed_lattice(n, 3), N)
-    res = compare(g, o, label="uniform")
+    res = compare(g, o, label="uniform", seeds=oracle.seed_lattice(n, 3), n=n)
     assert g["stats"]["particle_steps"] == int(np.where(o["flag"] == 0, N, o["exit"] + 1).sum())
     # exit points: where the straight line x0 + u t leaves the box
     seeds = oracle.seed_lattice(n, 3)
@@ -151,8 +151,8 @@ def test_ragged_block_and_lattice_all_dtypes():
         _say(f"ragged 37x23x19 stride 3 {dt}")
         gr = s.grids(dt)
         g = run_gpu(n, _dev(gr, dt), s.times, stride=3, record_exit=True)
-        _, o = oracle_lattice(oracle.Field(n, gr, dtype=dt), s.times, n, 3, N)
-        res = compare(g, o, label=dt)
+        sd, o = oracle_lattice(oracle.Field(n, gr, dtype=dt), s.times, n, 3, N)
+        res = compare(g, o, label=dt, seeds=sd, n=n)
         assert 0.0 < res["terminated"] < 1.0
 
 
@@ -572,5 +572,5 @@ def test_largest_block_axis_closed_form_and_oracle():
         want = x0 + float(ux) * (times[e] - times[0])
         assert abs(g["end"][i, 0] - want) < 1e-5
     gl = run_gpu(n, dev, times, stride=3)
-    _, ol = oracle_lattice(oracle.Field(n, gr), times, n, 3, N)
-    compare(gl, ol, label="axis 1024 lattice")
+    sl, ol = oracle_lattice(oracle.Field(n, gr), times, n, 3, N)
+    compare(gl, ol, label="axis 1024 lattice", seeds=sl, n=n)
