@@ -178,17 +178,40 @@ int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
  *                       incoherent (mixed) particle sets.  16-bit storage
  *                       always uses 1;
  *   ckpt_every          steps between the checkpoints that BTO_RECORD_CKPT
- *                       records (>= 1, default 10).
+ *                       records (>= 1, default 10);
+ *   tiles               0 (default), 1 or 2.  With 1 or 2, every RK4 step is
+ *                       its own pair of launches over the live particles kept
+ *                       in buckets by tile of cells, one workgroup per tile,
+ *                       tiles in Morton order with one eighth of them per
+ *                       XCD; each survivor goes into the bucket of the tile it
+ *                       ends in, so the particles stay sorted by tile.  With 2
+ *                       (12^3-cell tiles) the particles gather from the grids.
+ *                       With 1 the workgroup first stages its tile's cells
+ *                       plus a 2-cell halo of both grid levels in LDS with
+ *                       coalesced loads and samples from there (12^3-cell
+ *                       tiles for 16-bit storage, 8^3 for FP32, so that two
+ *                       workgroups fit a CU's LDS); particles whose stage
+ *                       points leave the staged box are advanced from the
+ *                       grids by the second launch.  Results are identical to
+ *                       the default layout run one step per launch.  Pays for
+ *                       large blocks advanced one cycle per call (the in situ
+ *                       form).  Set before bto_seed* (it is latched for the
+ *                       interval); with 1, every advect call of the interval
+ *                       must use storage types of one tile size (BTO_EINVAL
+ *                       otherwise).  steps_per_launch, rebin_every,
+ *                       blocks_per_cu and lanes_per_particle do not apply.
+
  * Defaults come from the environment variables BTO_STEPS_PER_LAUNCH,
- * BTO_REBIN_EVERY, BTO_BLOCKS_PER_CU and BTO_LANES_PER_PARTICLE when the
- * context is created.  BTO_EINVAL for values out of range; takes effect on
- * the next advect call. */
+ * BTO_REBIN_EVERY, BTO_BLOCKS_PER_CU, BTO_LANES_PER_PARTICLE and BTO_TILES
+ * when the context is created.  BTO_EINVAL for values out of range; takes
+ * effect on the next advect call (tiles: on the next seeding). */
 typedef struct {
     int32_t steps_per_launch;
     int32_t rebin_every;
     int32_t blocks_per_cu;
     int32_t lanes_per_particle;
     int32_t ckpt_every;
+    int32_t tiles;
 } bto_tuning;
 
 int bto_set_tuning(bto_ctx *ctx, const bto_tuning *t);

@@ -46,7 +46,7 @@ class Block(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("steps_per_launch", ctypes.c_int32), ("rebin_every", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("lanes_per_particle", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("tiles", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

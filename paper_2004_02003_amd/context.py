@@ -93,12 +93,13 @@ class Context:
         self._check(self.L.bto_get_tuning(self._h, ctypes.byref(t)))
         return dict(steps_per_launch=t.steps_per_launch, rebin_every=t.rebin_every,
                     blocks_per_cu=t.blocks_per_cu, lanes_per_particle=t.lanes_per_particle,
-                    ckpt_every=t.ckpt_every)
+                    ckpt_every=t.ckpt_every, tiles=t.tiles)
 
     def set_tuning(self, steps_per_launch=None, rebin_every=None, blocks_per_cu=None,
-                   lanes_per_particle=None, ckpt_every=None):
+                   lanes_per_particle=None, ckpt_every=None, tiles=None):
         """Launch shape of the advection (events unchanged; positions agree
-        to FP32 rounding) and the spacing of recorded checkpoints."""
+        to FP32 rounding), the spacing of recorded checkpoints, and the tile
+        layout (tile-staged steps; latched at the next seeding)."""
         cur = self.tuning()
         t = _lib.Tuning()
         t.steps_per_launch = cur["steps_per_launch"] if steps_per_launch is None else int(steps_per_launch)
@@ -107,6 +108,7 @@ class Context:
         t.lanes_per_particle = (cur["lanes_per_particle"] if lanes_per_particle is None
                                 else int(lanes_per_particle))
         t.ckpt_every = cur["ckpt_every"] if ckpt_every is None else int(ckpt_every)
+        t.tiles = cur["tiles"] if tiles is None else int(tiles)
         self._check(self.L.bto_set_tuning(self._h, ctypes.byref(t)))
 
     # -- the path ----------------------------------------------------------

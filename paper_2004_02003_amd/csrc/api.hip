@@ -67,6 +67,21 @@ struct bto_ctx {
     void* grec_buf = nullptr;
     size_t grec_bytes = 0;
     bool grad_atomics = false;    // BTO_GRAD_ATOMICS=1: add grid gradients with FP32 atomics instead
+    // tile layout (tile-staged steps; tuning `tiles`, latched at seeding)
+    int tiles = 0;
+    bool tile_on = false;         // this interval advances in the tile layout
+    bool tile_layout = false;     // live particles are in the buckets (else in the segments)
+    TileGeom tg{};
+    uint32_t ntiles = 0, tcap = 0;
+    int tile_grid = 0;            // workgroups of a tile step (8 x the largest octant of tiles)
+    void* tile_buf = nullptr;     // [order | 3 x ntiles counts | 3 list counts | buckets x 2]
+    size_t tile_bytes = 0;
+    int32_t* tile_order = nullptr;
+    uint32_t* tcount = nullptr;
+    uint32_t* lcount = nullptr;
+    PState* bpos[2] = {nullptr, nullptr};
+    uint32_t* bid[2] = {nullptr, nullptr};
+    int tb = 0;                   // bucket buffer of the current step
     std::string err;
 };
 
@@ -147,6 +162,10 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     if (const char* e = std::getenv("BTO_OCTANT_SEED")) c->octant_seed = std::atoi(e) != 0;
     if (const char* e = std::getenv("BTO_LANES_PER_PARTICLE")) c->lanes_per_particle = std::atoi(e) == 2 ? 2 : 1;
     if (const char* e = std::getenv("BTO_GRAD_ATOMICS")) c->grad_atomics = std::atoi(e) != 0;
+    if (const char* e = std::getenv("BTO_TILES")) {
+        const int v = std::atoi(e);
+        c->tiles = v >= 0 && v <= 2 ? v : 0;
+    }
     if (const char* e = std::getenv("BTO_BRICK")) {
         int b0 = 0, b1 = 0, b2 = 0;
         if (std::sscanf(e, "%d,%d,%d", &b0, &b1, &b2) == 3 && b0 > 0 && b1 > 0 && b2 > 0 && b0 * b1 * b2 == 64) {
@@ -198,6 +217,7 @@ int bto_destroy(bto_ctx* c) {
     if (c->grec_buf) (void)hipFree(c->grec_buf);
     if (c->rebin_buf) (void)hipFree(c->rebin_buf);
     if (c->rebin_temp) (void)hipFree(c->rebin_temp);
+    if (c->tile_buf) (void)hipFree(c->tile_buf);
     delete c;
     return BTO_OK;
 }
@@ -226,6 +246,205 @@ static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hip
     c->steps_since_rebin = 0;
     c->ck_k = 0;
     c->ck_ok = true;
+    c->tile_on = c->tiles != 0;
+    c->tile_layout = false;
+    return BTO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile layout.
+// ---------------------------------------------------------------------------
+static uint32_t spread3(uint32_t v) {  // bits of v at every third position
+    uint32_t r = 0;
+    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+
+// Tile geometry of storage type dtype, buckets sized for the current seeds,
+// and the tile order: workgroups run round-robin over the 8 XCDs, and XCD x
+// takes the x-th eighth of the tiles in Morton order (neighbouring tiles run
+// close in time on one XCD and share their halo lines in its L2).
+static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
+    TileGeom tg{};
+    tg.T = tile_side(dtype, c->tiles == 1);
+    tg.H = TILE_H;
+    uint64_t ntiles = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int cells = c->blk.n[d] - 1;
+        tg.nt[d] = (cells + tg.T - 1) / tg.T;
+        ntiles *= (uint64_t)tg.nt[d];
+    }
+    if (ntiles > 0xFFFFFFFFull / 2) return fail(c, BTO_ERANGE, "too many tiles");
+    uint64_t per = ((uint64_t)c->n_seeds + ntiles - 1) / ntiles;
+    uint64_t cap = 2 * per + 32;
+    if (cap < 64) cap = 64;
+    cap = (cap + 31) & ~(uint64_t)31;
+    if (ntiles * cap > 0xFFFFFFFFull) return fail(c, BTO_ERANGE, "tile buckets exceed 2^32 slots");
+    // the same geometry and bucket size as the last interval: everything is in place
+    if (c->tile_buf && c->tg.T == tg.T && c->ntiles == (uint32_t)ntiles && c->tcap == (uint32_t)cap) return BTO_OK;
+    // workgroup order: all tiles in Morton order, cut into NSEG equal
+    // contiguous runs, run x for XCD x; order[k * NSEG + x] = k-th tile of run x
+    std::vector<std::pair<uint64_t, int32_t>> mt;
+    mt.reserve((size_t)ntiles);
+    for (int tz = 0; tz < tg.nt[2]; ++tz)
+        for (int ty = 0; ty < tg.nt[1]; ++ty)
+            for (int tx = 0; tx < tg.nt[0]; ++tx) {
+                const uint64_t key = (uint64_t)spread3((uint32_t)tx) | ((uint64_t)spread3((uint32_t)ty) << 1) |
+                                     ((uint64_t)spread3((uint32_t)tz) << 2);
+                mt.push_back({key, tx + tg.nt[0] * (ty + tg.nt[1] * tz)});
+            }
+    std::sort(mt.begin(), mt.end());
+    const size_t longest = ((size_t)ntiles + NSEG - 1) / NSEG;
+    const int grid = (int)(longest * NSEG);
+    std::vector<int32_t> order((size_t)grid, -1);
+    for (int x = 0; x < NSEG; ++x) {
+        const size_t b = (size_t)ntiles * x / NSEG, e = (size_t)ntiles * (x + 1) / NSEG;
+        for (size_t k = b; k < e; ++k) order[(k - b) * NSEG + x] = mt[k].second;
+    }
+    const size_t o_bytes = ((size_t)grid * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t c_bytes = ((3 * (size_t)ntiles + 3) * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t b_bytes = (size_t)ntiles * cap * (sizeof(PState) + sizeof(uint32_t));
+    const size_t need = o_bytes + c_bytes + 2 * b_bytes;
+    if (need > c->tile_bytes) {
+        if (c->tile_buf) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(c, e, "tile buffers sync");
+            (void)hipFree(c->tile_buf);
+            c->tile_buf = nullptr;
+            c->tile_bytes = 0;
+        }
+        if (hipMalloc(&c->tile_buf, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, BTO_ENOMEM, "tile buffers of %zu bytes", need);
+        }
+        c->tile_bytes = need;
+    }
+    char* q = static_cast<char*>(c->tile_buf);
+    c->tile_order = reinterpret_cast<int32_t*>(q);
+    c->tcount = reinterpret_cast<uint32_t*>(q + o_bytes);
+    c->lcount = c->tcount + 3 * (size_t)ntiles;
+    char* b = q + o_bytes + c_bytes;
+    for (int k = 0; k < 2; ++k) {
+        c->bpos[k] = reinterpret_cast<PState*>(b + k * b_bytes);
+        c->bid[k] = reinterpret_cast<uint32_t*>(b + k * b_bytes + (size_t)ntiles * cap * sizeof(PState));
+    }
+    hipError_t e = hipMemcpyAsync(c->tile_order, order.data(), (size_t)grid * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // `order` is a host temporary
+    if (e != hipSuccess) return hip_fail(c, e, "tile order upload");
+    c->tg = tg;
+    c->ntiles = (uint32_t)ntiles;
+    c->tcap = (uint32_t)cap;
+    c->tile_grid = grid;
+    return BTO_OK;
+}
+
+// Move the live particles of the segments into the buckets of the coming
+// step (all tile and list counts zeroed first; the count ring keeps its slot).
+static int tile_enter(bto_ctx* c, int dtype, int max_seg_blocks, hipStream_t s) {
+    int rc = tile_setup(c, dtype, s);
+    if (rc) return rc;
+    hipError_t e = launch_tile_fill(c->tcount, 3 * (size_t)c->ntiles + 3, s);
+    if (e != hipSuccess) return hip_fail(c, e, "tile count fill");
+    TileBinArgs a{};
+    a.g = c->geom;
+    a.tg = c->tg;
+    a.segs = c->segs;
+    a.count = c->counts + NSEG * c->slot;
+    a.pos = c->pos[c->cur];
+    a.id = c->id[c->cur];
+    c->tb = 0;
+    c->cur = 1 - c->cur;  // the list of the coming step lives in the other particle buffer
+    a.out.tc = c->tcount + (size_t)c->slot * c->ntiles;
+    a.out.bpos = c->bpos[c->tb];
+    a.out.bid = c->bid[c->tb];
+    a.out.cap = c->tcap;
+    a.out.list_pos = c->pos[c->cur];
+    a.out.list_id = c->id[c->cur];
+    a.out.list_count = c->lcount + c->slot;
+    e = launch_tile_bin(a, max_seg_blocks, s);
+    if (e != hipSuccess) return hip_fail(c, e, "tile bin launch");
+    c->tile_layout = true;
+    return BTO_OK;
+}
+
+// Live particles of the tile layout, by seed id: flow-map entries (out_end
+// non-null) or FP64 positions into a checkpoint slot (ckpt non-null).
+static int tile_live(bto_ctx* c, double* out_end, uint8_t* out_flag, int32_t* out_exit, double* ckpt,
+                     hipStream_t s) {
+    TileLiveArgs a{};
+    a.ntiles = c->ntiles;
+    a.cap = c->tcap;
+    a.tc = c->tcount + (size_t)c->slot * c->ntiles;
+    a.bpos = c->bpos[c->tb];
+    a.bid = c->bid[c->tb];
+    a.list_pos = c->pos[c->cur];
+    a.list_id = c->id[c->cur];
+    a.list_count = c->lcount + c->slot;
+    a.list_n_max = (uint64_t)c->n_seeds;
+    a.steps_done = c->steps_done;
+    for (int d = 0; d < 3; ++d) {
+        a.origin[d] = c->blk.origin[d];
+        a.spacing[d] = c->blk.spacing[d];
+    }
+    a.out_end = out_end;
+    a.out_flag = out_flag;
+    a.out_exit = out_exit;
+    a.ckpt = ckpt;
+    hipError_t e = launch_tile_live(a, s);
+    return e == hipSuccess ? BTO_OK : hip_fail(c, e, "tile live launch");
+}
+
+// One RK4 step of every live particle in the tile layout: the tile launch,
+// then the list launch; the rings advance by one.
+static int tile_step(bto_ctx* c, const void* f0, const void* f1, double h, int dtype, int mode, int rec,
+                     hipStream_t s) {
+    const int sl = c->slot, sl1 = (c->slot + 1) % 3, sl2 = (c->slot + 2) % 3;
+    TileStepArgs a{};
+    a.f0 = static_cast<const char*>(f0);
+    a.f1 = static_cast<const char*>(f1);
+    a.h = h;
+    a.g = c->geom;
+    a.tg = c->tg;
+    a.step0 = c->steps_done;
+    a.order = c->tile_order;
+    a.order_len = c->tile_grid;
+    a.tc_in = c->tcount + (size_t)sl * c->ntiles;
+    a.tc_clear = c->tcount + (size_t)sl2 * c->ntiles;
+    a.in_pos = c->bpos[c->tb];
+    a.in_id = c->bid[c->tb];
+    a.out.tc = c->tcount + (size_t)sl1 * c->ntiles;
+    a.out.bpos = c->bpos[1 - c->tb];
+    a.out.bid = c->bid[1 - c->tb];
+    a.out.cap = c->tcap;
+    a.out.list_pos = c->pos[1 - c->cur];
+    a.out.list_id = c->id[1 - c->cur];
+    a.out.list_count = c->lcount + sl1;
+    a.list_pos = c->pos[c->cur];
+    a.list_id = c->id[c->cur];
+    a.list_count = c->lcount + sl;
+    a.list_clear = c->lcount + sl2;
+    a.rec_pos = c->rec_pos;
+    a.rec_meta = c->rec_meta;
+    a.rec_out = c->rec_out;
+    a.psteps = c->psteps;
+    a.live_out = c->counts + NSEG * sl1;
+    a.live_clear = c->counts + NSEG * sl2;
+    hipError_t e = launch_tile_step(a, dtype, mode, rec, c->tiles == 1 ? 1 : 0, s);
+    if (e != hipSuccess) return hip_fail(c, e, "tile step launch");
+    TileListArgs l{};
+    l.s = a;
+    l.in_pos = c->pos[c->cur];
+    l.in_id = c->id[c->cur];
+    l.in_count = c->lcount + sl;
+    int64_t lg = c->n_seeds / (BLOCK * 32);
+    lg = lg < 64 ? 64 : (lg > 1024 ? 1024 : lg);
+    e = launch_tile_list(l, dtype, mode, rec, (int)lg, s);
+    if (e != hipSuccess) return hip_fail(c, e, "tile list launch");
+    c->slot = sl1;
+    c->cur = 1 - c->cur;
+    c->tb = 1 - c->tb;
+    c->steps_done += 1;
     return BTO_OK;
 }
 
@@ -429,6 +648,25 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     }
     int64_t max_seg = 0;
     for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
+    if (c->tile_on) {
+        if (c->tile_layout && tile_side(dtype, c->tiles == 1) != c->tg.T)
+            return fail(c, BTO_EINVAL, "this interval's tile layout has %d-cell tiles; storage type %d needs %d",
+                        c->tg.T, dtype, tile_side(dtype, c->tiles == 1));
+        if (!c->tile_layout) {
+            rc = tile_enter(c, dtype, blocks_per_seg(c, max_seg, 4), s);
+            if (rc) return rc;
+        }
+        for (int32_t q = 0; q < n_steps; ++q) {
+            if (store_ck && c->steps_done % c->ck_k == 0) {
+                rc = tile_live(c, nullptr, nullptr, nullptr,
+                               c->ck_rec + (size_t)(c->steps_done / c->ck_k) * (size_t)c->cap * 3, s);
+                if (rc) return rc;
+            }
+            rc = tile_step(c, d_fields[q], d_fields[q + 1], times[q + 1] - times[q], dtype, mode, rec, s);
+            if (rc) return rc;
+        }
+        return BTO_OK;
+    }
     const int lpp = dtype == BTO_F32 ? c->lanes_per_particle : 1;
     int per_cu = advect_max_blocks_per_cu(dtype, mode, lpp, rec);
     if (c->blocks_per_cu_cap > 0 && c->blocks_per_cu_cap < per_cu) per_cu = c->blocks_per_cu_cap;
@@ -517,8 +755,13 @@ int bto_flowmap_out(bto_ctx* c, double* d_seed_xyz, double* d_end_xyz, uint8_t* 
         a.out_exit = d_exit_step;
         int64_t max_seg = 0;
         for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
-        hipError_t e = launch_flowmap(a, blocks_per_seg(c, max_seg, 4), s);
+        // the segment writer only when the live particles are in the segments
+        hipError_t e = launch_flowmap(a, c->tile_layout ? 0 : blocks_per_seg(c, max_seg, 4), s);
         if (e != hipSuccess) return hip_fail(c, e, "flowmap launch");
+        if (c->tile_layout) {
+            rc = tile_live(c, d_end_xyz, d_flag, d_exit_step, nullptr, s);
+            if (rc) return rc;
+        }
     }
     if (n_valid_out) {
         bto_stats_t st;
@@ -828,6 +1071,8 @@ int bto_set_tuning(bto_ctx* c, const bto_tuning* t) {
     if (t->lanes_per_particle != 1 && t->lanes_per_particle != 2)
         return fail(c, BTO_EINVAL, "lanes_per_particle must be 1 or 2");
     if (t->ckpt_every < 1) return fail(c, BTO_EINVAL, "ckpt_every must be >= 1");
+    if (t->tiles < 0 || t->tiles > 2) return fail(c, BTO_EINVAL, "tiles must be 0, 1 or 2");
+    c->tiles = t->tiles;
     c->lanes_per_particle = t->lanes_per_particle;
     c->ckpt_every = t->ckpt_every;
     c->steps_per_launch = t->steps_per_launch;
@@ -843,6 +1088,7 @@ int bto_get_tuning(const bto_ctx* c, bto_tuning* t) {
     t->blocks_per_cu = c->blocks_per_cu_cap;
     t->lanes_per_particle = c->lanes_per_particle;
     t->ckpt_every = c->ckpt_every;
+    t->tiles = c->tiles;
     return BTO_OK;
 }
 

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace bto {
 
 constexpr int KMAX = 128;  // RK4 steps fused into one launch (one per cycle)
@@ -25,6 +27,10 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
 
 enum : int { S_VALID = 0, S_TERMINATED = 1, S_INVALID = 2 };
+// Internal outcome of a step sampled from a staged tile: a stage point needs
+// grid values outside the staged box, so the step is left undone (x kept at
+// the step's start) and redone from the global grids.  Never recorded.
+constexpr int S_DEFER = 3;
 enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 enum : int { MODE_LINEAR = 0, MODE_FROZEN = 1 };
 // Per-seed record of an ended particle: flag << 28 | bits below | exit step.
@@ -76,20 +82,20 @@ __device__ __forceinline__ bool inside(const Geom& g, const double p[3]) {
 // Sampling cell i_d = min(floor(p_d), n_d - 2) and FP32 offset f_d = p_d - i_d.
 struct Cell {
     uint32_t base;  // point index of corner (i, j, k)
+    int i[3];       // the cell indices (i, j, k)
     float f[3];
 };
 
 __device__ __forceinline__ Cell locate(const Geom& g, const double p[3]) {
     Cell c;
-    int i[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         int v = (int)floor(p[d]);
         v = v > g.n[d] - 2 ? g.n[d] - 2 : v;
-        i[d] = v;
+        c.i[d] = v;
         c.f[d] = (float)(p[d] - (double)v);
     }
-    c.base = (uint32_t)i[0] + g.sy * (uint32_t)i[1] + g.sz * (uint32_t)i[2];
+    c.base = (uint32_t)c.i[0] + g.sy * (uint32_t)c.i[1] + g.sz * (uint32_t)c.i[2];
     return c;
 }
 
@@ -107,28 +113,55 @@ constexpr uint32_t NO_CELL = 0xFFFFFFFFu;
 struct __attribute__((packed, aligned(4))) Row32 { float v[6]; };
 struct __attribute__((packed, aligned(2))) Row16 { uint32_t w[3]; };
 
+// Value (r, q) of a row of two 16-bit points packed as three dwords
+// (x0|y0, z0|x1, y1|z1), converted to FP32 (exact).
+template <int DT>
+__device__ __forceinline__ float dec16(uint32_t w, int hi) {
+    const uint32_t h = hi ? (w >> 16) : (w & 0xFFFFu);
+    if constexpr (DT == DT_F16) {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)h);
+    } else {
+        return __uint_as_float(h << 16);
+    }
+}
+
 template <int DT>
 struct CellCache {
     uint32_t base;
     float R[4][6];
     __device__ __forceinline__ float v(int r, int q) const { return R[r][q]; }
     __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
-        if constexpr (DT == DT_F32) {
-            const Row32 x = *reinterpret_cast<const Row32*>(V + (uint64_t)pt * 12u);
+        const Row32 x = *reinterpret_cast<const Row32*>(V + (uint64_t)pt * 12u);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) R[r][q] = x.v[q];
-        } else {
-            const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const uint32_t w = x.w[q >> 1];
-                if constexpr (DT == DT_F16) {
-                    R[r][q] = (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> ((q & 1) * 16)));
-                } else {
-                    R[r][q] = __uint_as_float((q & 1) ? (w & 0xFFFF0000u) : (w << 16));
-                }
-            }
-        }
+        for (int q = 0; q < 6; ++q) R[r][q] = x.v[q];
+    }
+};
+
+// 16-bit grids: the rows stay packed in registers (12 instead of 24 per
+// level) and are converted to FP32 where the sampler reads them.
+template <>
+struct CellCache<DT_F16> {
+    uint32_t base;
+    uint32_t W[4][3];
+    __device__ __forceinline__ float v(int r, int q) const { return dec16<DT_F16>(W[r][q >> 1], q & 1); }
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
+        const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
+        W[r][0] = x.w[0];
+        W[r][1] = x.w[1];
+        W[r][2] = x.w[2];
+    }
+};
+
+template <>
+struct CellCache<DT_BF16> {
+    uint32_t base;
+    uint32_t W[4][3];
+    __device__ __forceinline__ float v(int r, int q) const { return dec16<DT_BF16>(W[r][q >> 1], q & 1); }
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
+        const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
+        W[r][0] = x.w[0];
+        W[r][1] = x.w[1];
+        W[r][2] = x.w[2];
     }
 };
 
@@ -300,6 +333,76 @@ __device__ __forceinline__ void trilerp_grad(const CA& A, const CA& B, const flo
     }
 }
 
+// ---------------------------------------------------------------------------
+// Grid levels staged in LDS for one tile of cells (the tile kernels): every
+// grid point of the staging box, S points per axis starting at point lo,
+// x fastest, one entry per point -- (x, y, z, 0) as FP32 (16 bytes) for FP32
+// grids, as the stored 16-bit values (8 bytes) otherwise; one plane per
+// level.  A cell is available when both of its corner points along every axis
+// lie in the staged part of the box (lim = staged points - 2 per axis).  The
+// values handed to the sampler are the same FP32 numbers a global row load
+// produces, so a step sampled from LDS is bit-identical to one sampled from
+// the grids.
+// ---------------------------------------------------------------------------
+template <int DT>
+struct LdsCache {
+    uint32_t base;  // grid point index of the cached cell (NO_CELL: none)
+    // FP32: the values; 16-bit: each row packed as three dwords as in CellCache
+    typename std::conditional<DT == DT_F32, float[4][6], uint32_t[4][3]>::type R;
+    const char* plane;  // this level's plane in LDS
+    int lo[3], lim[3];
+    int S;
+    __device__ __forceinline__ float v(int r, int q) const {
+        if constexpr (DT == DT_F32) {
+            return R[r][q];
+        } else {
+            return dec16<DT>(R[r][q >> 1], q & 1);
+        }
+    }
+    __device__ __forceinline__ void load_row(uint32_t li, int r) {
+        if constexpr (DT == DT_F32) {
+            const float4 a = *reinterpret_cast<const float4*>(plane + (size_t)li * 16u);
+            const float4 b = *reinterpret_cast<const float4*>(plane + (size_t)li * 16u + 16u);
+            R[r][0] = a.x;
+            R[r][1] = a.y;
+            R[r][2] = a.z;
+            R[r][3] = b.x;
+            R[r][4] = b.y;
+            R[r][5] = b.z;
+        } else {
+            // entries (x0|y0, z0|0, x1|y1, z1|0) -> (x0|y0, z0|x1, y1|z1)
+            const uint4 a = *reinterpret_cast<const uint4*>(plane + (size_t)li * 8u);
+            R[r][0] = a.x;
+            R[r][1] = (a.y & 0xFFFFu) | (a.z << 16);
+            R[r][2] = (a.z >> 16) | (a.w << 16);
+        }
+    }
+};
+
+// Bring a cell's corner values into the cache.  Global caches always succeed;
+// an LDS cache fails when the cell lies outside the staged box.
+template <int DT, class Cache>
+__device__ __forceinline__ bool fetch(const Geom& g, const char* V, const Cell& c, Cache& k) {
+    ensure<DT>(g, V, c.base, k);
+    return true;
+}
+
+template <int DT>
+__device__ __forceinline__ bool fetch(const Geom&, const char*, const Cell& c, LdsCache<DT>& k) {
+    if (k.base == c.base) return true;
+    const int lx = c.i[0] - k.lo[0], ly = c.i[1] - k.lo[1], lz = c.i[2] - k.lo[2];
+    if ((unsigned)lx > (unsigned)k.lim[0] || (unsigned)ly > (unsigned)k.lim[1] || (unsigned)lz > (unsigned)k.lim[2])
+        return false;
+    const uint32_t li = (uint32_t)lx + (uint32_t)k.S * ((uint32_t)ly + (uint32_t)k.S * (uint32_t)lz);
+    const uint32_t S = (uint32_t)k.S, S2 = S * S;
+    k.load_row(li, 0);
+    k.load_row(li + S, 1);
+    k.load_row(li + S2, 2);
+    k.load_row(li + S + S2, 3);
+    k.base = c.base;
+    return true;
+}
+
 __device__ __forceinline__ bool finite3(const float k[3]) {
     return __builtin_isfinite(k[0]) && __builtin_isfinite(k[1]) && __builtin_isfinite(k[2]);
 }
@@ -355,7 +458,8 @@ __device__ __forceinline__ void exit_face(const Geom& g, const double x[3], cons
 }
 
 // One RK4 step.  On termination x keeps the last inside position and
-// `on_exit(y)` is called with the outside point that ended the particle.
+// `on_exit(y)` is called with the outside point that ended the particle.  With
+// LDS caches the step may return S_DEFER (x unchanged) before any event.
 template <int DT, int MODE, class Cache, class OnExit>
 __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, double* x,
                                         Cache& LA, Cache& LB, OnExit&& on_exit) {
@@ -365,7 +469,7 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     Cell c;
 
     c = locate(g, x);
-    ensure<DT>(g, V0, c.base, LA);
+    if (!fetch<DT>(g, V0, c, LA)) return S_DEFER;
     trilerp(LA, c.f, k1);
     if (!finite3(k1)) return S_INVALID;
 #pragma unroll
@@ -376,9 +480,9 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     }
 
     c = locate(g, y);
-    ensure<DT>(g, V0, c.base, LA);
+    if (!fetch<DT>(g, V0, c, LA)) return S_DEFER;
     if (MODE == MODE_LINEAR) {
-        ensure<DT>(g, V1, c.base, LB);
+        if (!fetch<DT>(g, V1, c, LB)) return S_DEFER;
         trilerp_mid(LA, LB, c.f, k2);
     } else {
         trilerp(LA, c.f, k2);
@@ -392,9 +496,9 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     }
 
     c = locate(g, y);
-    ensure<DT>(g, V0, c.base, LA);
+    if (!fetch<DT>(g, V0, c, LA)) return S_DEFER;
     if (MODE == MODE_LINEAR) {
-        ensure<DT>(g, V1, c.base, LB);
+        if (!fetch<DT>(g, V1, c, LB)) return S_DEFER;
         trilerp_mid(LA, LB, c.f, k3);
     } else {
         trilerp(LA, c.f, k3);
@@ -409,10 +513,10 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
 
     c = locate(g, y);
     if (MODE == MODE_LINEAR) {
-        ensure<DT>(g, V1, c.base, LB);
+        if (!fetch<DT>(g, V1, c, LB)) return S_DEFER;
         trilerp(LB, c.f, k4);
     } else {
-        ensure<DT>(g, V0, c.base, LA);
+        if (!fetch<DT>(g, V0, c, LA)) return S_DEFER;
         trilerp(LA, c.f, k4);
     }
     if (!finite3(k4)) return S_INVALID;

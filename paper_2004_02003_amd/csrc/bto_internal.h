@@ -170,6 +170,107 @@ struct RebinArgs {
     size_t temp_bytes;
 };
 
+// ---------------------------------------------------------------------------
+// Tile layout of the live particles (tile-staged advection, tiles.hip).
+// ---------------------------------------------------------------------------
+constexpr int TILE_H = 2;       // halo cells staged around a tile
+constexpr int TILE_S_16 = 17;   // staging box side in points, 16-bit grids (tile of 12 cells)
+constexpr int TILE_S_F32 = 13;  // FP32 grids (tile of 8 cells)
+
+// Tile side in cells: staged tiles are sized so that two workgroups' boxes
+// fit a CU's LDS; gathering tiles take the 16-bit staged size for every type.
+__host__ __device__ constexpr int tile_side(int dtype, int staged) {
+    return (staged && dtype == DT_F32 ? TILE_S_F32 : TILE_S_16) - 1 - 2 * TILE_H;
+}
+
+struct __attribute__((packed, aligned(2))) Pt16 {
+    uint32_t xy;
+    uint16_t z;
+};
+
+struct TileGeom {
+    int32_t T, H;       // tile side and halo (cells)
+    int32_t nt[3];      // tiles per axis
+};
+
+struct TileOut {
+    uint32_t* tc;       // tile counts of the next step (appended)
+    PState* bpos;       // next step's buckets: ntiles x cap
+    uint32_t* bid;
+    uint32_t cap;
+    PState* list_pos;   // next step's list (bucket overflow)
+    uint32_t* list_id;
+    uint32_t* list_count;
+};
+
+struct TileStepArgs {
+    const char* f0;           // grid of cycle n
+    const char* f1;           // grid of cycle n + 1
+    double h;
+    Geom g;
+    TileGeom tg;
+    int32_t step0;            // index of this step in the interval
+    const int32_t* order;     // order[k * NSEG + x]: k-th tile of XCD x's run (-1: none)
+    int32_t order_len;        // entries of order (a multiple of NSEG)
+    const uint32_t* tc_in;    // this step's tile counts
+    uint32_t* tc_clear;       // tile counts cleared for the step after next
+    const PState* in_pos;     // this step's buckets
+    const uint32_t* in_id;
+    TileOut out;
+    PState* list_pos;         // this step's list (deferred particles appended)
+    uint32_t* list_id;
+    uint32_t* list_count;
+    uint32_t* list_clear;     // list count cleared for the step after next
+    PState* rec_pos;
+    int32_t* rec_meta;
+    float4* rec_out;
+    unsigned long long* psteps;
+    uint32_t* live_out;       // NSEG survivor counts of the next step
+    uint32_t* live_clear;     // NSEG counts cleared for the step after next
+};
+
+struct TileListArgs {
+    TileStepArgs s;
+    const PState* in_pos;     // this step's list
+    const uint32_t* in_id;
+    const uint32_t* in_count;
+};
+
+struct TileBinArgs {
+    Geom g;
+    TileGeom tg;
+    Segs segs;
+    const uint32_t* count;    // NSEG live counts of the segments
+    const PState* pos;
+    const uint32_t* id;
+    TileOut out;              // buckets and list of the coming step
+};
+
+struct TileLiveArgs {
+    uint32_t ntiles, cap;
+    const uint32_t* tc;
+    const PState* bpos;
+    const uint32_t* bid;
+    const PState* list_pos;
+    const uint32_t* list_id;
+    const uint32_t* list_count;
+    uint64_t list_n_max;
+    int32_t steps_done;
+    double origin[3], spacing[3];
+    double* out_end;          // flow map (ckpt == null)
+    uint8_t* out_flag;
+    int32_t* out_exit;
+    double* ckpt;             // checkpoint slot base: [seed id][xyz] (cell units)
+};
+
+// One workgroup per order entry; stage = 1: sample LDS-staged tiles, 0: gather
+// from the grids.
+hipError_t launch_tile_step(const TileStepArgs& a, int dtype, int mode, int rec, int stage, hipStream_t s);
+hipError_t launch_tile_list(const TileListArgs& a, int dtype, int mode, int rec, int grid, hipStream_t s);
+hipError_t launch_tile_bin(const TileBinArgs& a, int blocks_per_seg, hipStream_t s);
+hipError_t launch_tile_fill(uint32_t* p, size_t n, hipStream_t s);
+hipError_t launch_tile_live(const TileLiveArgs& a, hipStream_t s);
+
 hipError_t launch_seed_lattice(const SeedLatticeArgs& a, hipStream_t s);
 hipError_t launch_seed_explicit(const SeedExplicitArgs& a, hipStream_t s);
 hipError_t launch_set_counts(uint32_t* counts, const uint32_t* values, int n, unsigned long long* psteps,

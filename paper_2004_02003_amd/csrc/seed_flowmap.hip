@@ -244,7 +244,7 @@ hipError_t launch_ckpt_store(const CkptArgs& a, int R, hipStream_t s) {
 hipError_t launch_flowmap(const FlowmapArgs& a, int R, hipStream_t s) {
     hipLaunchKernelGGL(flowmap_records_kernel, dim3(grid_for(a.P)), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || R == 0) return e;  // R == 0: live particles written by the caller
     hipLaunchKernelGGL(flowmap_live_kernel, dim3(R * NSEG), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
