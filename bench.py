@@ -1,14 +1,21 @@
 """Benchmark of the per-block BTO path on one MI355X.
 
-One step = one interval of the hot path over the resident input: seed the
-lattice, advance every live particle by the interval's RK4 steps (one per
-cycle) with boundary termination and compaction, and write the flow map.
-Workload: the 128^3 time-varying ABC block with noise (101 cycles, dt 0.05,
-64^3 seeds at stride 2, 100-step interval), FP32 grids resident in HBM.
+One step = one interval of the hot path in the in situ form the paper times
+(one velocity grid arrives per simulation cycle; Section 2.2, Section 4.2):
+seed the lattice, then per cycle one RK4 step of every live particle with
+boundary termination and compaction over the two resident grids (cycles n and
+n+1), then write the flow map.  Headline workload: the 512^3 Fourier-mode
+turbulence block, FP16 storage with FP32 arithmetic, 256^3 = 16,777,216 seeds
+at stride 2, a 200-step interval over 201 cycles (dt 0.01).  Only two grids
+are resident: the device generator writes cycle c+1's grid into the slot the
+previous step no longer reads, on the same stream, outside the timed region.
 
-Prints one JSON line: particle-RK4-steps/s of the whole step, the roofline of
-the dominant kernel (the fused advection launch, timed with HIP events on the
-stream it runs on), and the FP64 oracle timed on the host cores.
+Prints one JSON line: particle-RK4-steps/s of the interval (seed + 200 steps +
+flow-map write, median of HIP-event times over the timed intervals; grid
+generation excluded and reported on its own), the roofline of the dominant
+kernel at the per-unit figure of two grid levels over 8 points plus 40 bytes
+of particle state per live particle-step (136 B for 16-bit storage, 232 B for
+FP32), and the FP64 oracle timed on the host cores.
 """
 
 from __future__ import annotations
@@ -28,8 +35,8 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-RK4-steps/s on 1 MI355X + %HBM peak; FP32 vs FP16 field at stated err"
 HBM_PEAK_GBS = 8000.0
 STATE_BYTES = 40          # 16 B state + 4 B id, read once and written once per launch
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "advect_f32_abc128_traffic.json")
-KERNEL_SOURCES = ["paper_2004_02003_amd/csrc/bto_device.h", "paper_2004_02003_amd/csrc/advect.hip"]
+KERNEL_SOURCES = ["paper_2004_02003_amd/csrc/bto_device.h", "paper_2004_02003_amd/csrc/bto_internal.h",
+                  "paper_2004_02003_amd/csrc/advect.hip", "paper_2004_02003_amd/csrc/tiles.hip"]
 
 
 def kernel_hash() -> str:
@@ -74,18 +81,6 @@ def launch_plan(n_steps: int, kmax: int, rb: int):
         kmax = rb
     nl = (n_steps + kmax - 1) // kmax
     return [n_steps // nl + (1 if l < n_steps % nl else 0) for l in range(nl)]
-
-
-def algorithmic_bytes(per_launch, dt: str, stride: int):
-    """Bytes the fused launches must move: per particle-step one new grid level
-    over the points its cell touches (stride^3 points per seed at the lattice
-    density, i.e. 8 at stride 2), the first level once per launch, and the
-    particle state in and out once per launch."""
-    bpt = field_bytes_per_point(dt) * (stride ** 3 if stride <= 2 else 8)
-    total = 0
-    for live_in, psteps in per_launch:
-        total += bpt * (psteps + live_in) + STATE_BYTES * live_in
-    return total
 
 
 # Per-cycle time of the paper's own metric (Section 4.2: mean time per
@@ -143,14 +138,6 @@ def paper_context(log):
     return out
 
 
-# Launch shape per workload (results do not depend on it).  The coherent ABC
-# block runs best as seeded; the turbulent blocks mix their particles, so a
-# periodic re-sort restores cache locality, and for FP32 grids two lanes per
-# particle halve the cache lines a row load touches.
-LAUNCH_SHAPE = {
-    "turb_256": dict(rebin_every=5, lanes_per_particle=2),
-    "turb_512": dict(rebin_every=10, lanes_per_particle=2),
-}
 
 
 def posthoc_accuracy(log):
@@ -269,11 +256,13 @@ UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 
 def precision_statement(log, threads):
     """End-position error of the GPU path against the FP64 oracle on the FP64
-    field, per storage type, for the turbulence blocks (the 256^3 precision
-    workload in f32/f16/bf16, the 512^3 scale workload in f16 through a
-    two-slot ring), on a fixed seed subset; with the first-order bound
-    ||J|| N h max|V| (u_storage + 2^-21) per seed (J from the oracle's tangent,
-    u the storage's unit roundoff, 2^-21 the FP32 sampling arithmetic)."""
+    field, per storage type, for the turbulence blocks: the 256^3 precision
+    workload in f32/f16/bf16 on every 509th seed (4,121 seeds), and the 512^3
+    scale workload in f16 on every 256th seed (65,536 seeds), both through a
+    two-slot ring with one call per cycle.  Mean, p99 and max over the seeds
+    valid on both sides, the share beyond 1e-5 cells, and the first-order bound
+    ||J|| N h max|V| sqrt(3) (u_storage + 2^-21) per seed (J from the oracle's
+    FP64 tangent, u the storage's unit roundoff, 2^-21 the FP32 sampling)."""
     import torch
     import oracle
     from bto_inputs import _turb
@@ -281,7 +270,7 @@ def precision_statement(log, threads):
     from paper_2004_02003_amd import Context
 
     out = {}
-    for name, every in (("turb_256", 509), ("turb_512", 32771)):  # steps coprime with the lattice rows
+    for name, every in (("turb_256", 509), ("turb_512", 256)):  # 509: coprime with the lattice rows
         wl = WORKLOADS[name]
         s = wl.make_field()
         gen = _turb.DeviceTurbulence(s.lazy)
@@ -292,39 +281,39 @@ def precision_statement(log, threads):
         o = oracle.flowmap(oracle.Field.lazy_turbulence(s, "f64"), s.times, seeds, N, jac=True, nthreads=threads)
         log(f"precision {name}: FP64 oracle on {len(ids)} seeds in {time.perf_counter() - t0:.1f} s")
         nJ = np.linalg.norm(o["jac"], axis=(1, 2), ord=2)
-        shape = (wl.n[2], wl.n[1], wl.n[0], 3)
         res = {}
         for dt in wl.dtypes:
-            tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dt]
             vmax = 0.0
+            ring = Ring(gen, wl.n, dt)
             with Context(wl.n, wl.n_seeds) as ctx:
-                ctx.set_tuning(**{k: v for k, v in LAUNCH_SHAPE.get(name, {}).items()})
+                ctx.set_tuning(**insitu_shape(name, dt))
                 ctx.seed(wl.stride)
-                slots = [torch.empty(shape, dtype=tdt, device="cuda") for _ in range(2)]
-                gen.fill(0, dt, slots[0])
+                p_prev = ring.ptr(0)
                 for c in range(N):
-                    gen.fill(c + 1, dt, slots[(c + 1) % 2])
+                    p_next = ring.ptr(c + 1)
                     if c % 10 == 0:
-                        vmax = max(vmax, float(slots[(c + 1) % 2].float().abs().max()))
-                    ctx.advect([slots[c % 2], slots[(c + 1) % 2]], s.times[c:c + 2])
+                        vmax = max(vmax, float(ring.slots[(c + 1) % 2].float().abs().max()))
+                    ctx.advect_ptrs([p_prev, p_next], s.times[c:c + 2], DCODE[dt])
+                    p_prev = p_next
                 fm = ctx.flowmap()
                 torch.cuda.synchronize()
                 end = fm["end"].cpu().numpy()[ids]
                 flag = fm["flag"].cpu().numpy()[ids]
-                del slots
+            del ring
             torch.cuda.empty_cache()
             both = (flag == 0) & (o["flag"] == 0)
             err = np.linalg.norm(end[both] - o["end"][both], axis=1)
             bound = nJ[both] * N * wl.dt * vmax * np.sqrt(3.0) * (UNIT_ROUNDOFF[dt] + 2.0 ** -21)
             safe = o["margin"] >= 1e-6
             res[dt] = {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
-                       "n": int(both.sum()), "within_first_order_bound_pct": round(100.0 * float((err <= bound).mean()), 2),
+                       "n": int(both.sum()), "beyond_1e-5_pct": round(100.0 * float((err > 1e-5).mean()), 3),
+                       "within_first_order_bound_pct": round(100.0 * float((err <= bound).mean()), 2),
                        "bound_median": float(np.median(bound)),
                        "flag_disagree": int((flag != o["flag"]).sum()),
                        "flag_disagree_outside_margin": int(((flag != o["flag"]) & safe).sum())}
             log(f"precision {name} {dt}: {res[dt]}")
-        out[name] = {"seeds": f"every {every}th of {wl.n_seeds}", "steps": N, "cells": "end-position L2 error, cells",
-                     **res}
+        out[name] = {"seeds": f"every {every}th of {wl.n_seeds} ({len(ids)})", "steps": N,
+                     "cells": "end-position L2 error, cells", **res}
     return out
 
 
@@ -451,39 +440,373 @@ def differentiation(log):
     return out
 
 
-# Legs that --leg runs on their own (all of them but per_cycle are part of the
-# default run on the abc_128 workload).
+# Legs that --leg runs on their own (the default run adds the storage, ABC,
+# precision, differentiation and paper-context legs to the headline).
 LEGS = {
-    "paper_context": paper_context,
-    "posthoc_accuracy": posthoc_accuracy,
-    "insitu_overlap": lambda log: [insitu_overlap(log, 128, 32), insitu_overlap(log, 256, 64)],
-    "differentiation": differentiation,
-    "per_cycle": per_cycle,
+    "turb_256_storage": lambda log, copy_gbs: turb_storage_legs(log, copy_gbs),
+    "abc_128": lambda log, copy_gbs: abc_128_leg(log, copy_gbs),
+    "precision_turbulence": lambda log, copy_gbs: precision_statement(
+        log, int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()),
+    "paper_context": lambda log, copy_gbs: paper_context(log),
+    "posthoc_accuracy": lambda log, copy_gbs: posthoc_accuracy(log),
+    "insitu_overlap": lambda log, copy_gbs: [insitu_overlap(log, 128, 32), insitu_overlap(log, 256, 64)],
+    "differentiation": lambda log, copy_gbs: differentiation(log),
+    "per_cycle": lambda log, copy_gbs: per_cycle(log),
 }
+
+
+# --------------------------------------------------------------------------
+# The in situ form: one advect call per cycle over the grids of cycles n, n+1
+# --------------------------------------------------------------------------
+TDT = {"f32": "float32", "f16": "float16", "bf16": "bfloat16"}
+DCODE = {"f32": 0, "f16": 1, "bf16": 2}   # bto_dtype
+
+
+def insitu_bytes_per_pstep(dt: str) -> int:
+    """Per-unit figure of the in situ form: each live particle-step reads both
+    resident levels over the 8 points its cell touches at the stride-2 lattice
+    density, and reads and writes its 20 bytes of state: 2*8*b + 40 bytes."""
+    return 2 * 8 * field_bytes_per_point(dt) + STATE_BYTES
+
+
+class Ring:
+    """Two device slots filled cycle by cycle by the turbulence generator: the
+    grid of cycle c goes to slot c % 2, which the step of cycle c - 2 was the
+    last to read (same stream, so the overwrite waits for it)."""
+
+    def __init__(self, gen, n, dt):
+        import torch
+
+        self.gen, self.dt = gen, dt
+        shape = (n[2], n[1], n[0], 3)
+        self.slots = [torch.empty(shape, dtype=getattr(torch, TDT[dt]), device="cuda") for _ in range(2)]
+
+    def ptr(self, c: int, fill: bool = True) -> int:
+        if fill:
+            self.gen.fill(c, self.dt, self.slots[c % 2])
+        return self.slots[c % 2].data_ptr()
+
+
+def run_insitu_interval(ctx, stride, N, grid_ptr, times, dcode, out, ev=None):
+    """seed, N one-step advect calls, flow-map write.  grid_ptr(c) returns the
+    device pointer of cycle c's grid (a ring slot, filled on the stream before
+    the step that first reads it).  ev: (seed, steps[N], flowmap) event pairs."""
+    if ev is not None:
+        ev[0][0].record()
+    ctx.seed(stride)
+    if ev is not None:
+        ev[0][1].record()
+    p_prev = grid_ptr(0)
+    for c in range(N):
+        p_next = grid_ptr(c + 1)
+        if ev is not None:
+            ev[1][c][0].record()
+        ctx.advect_ptrs([p_prev, p_next], times[c:c + 2], dcode)
+        if ev is not None:
+            ev[1][c][1].record()
+        p_prev = p_next
+    if ev is not None:
+        ev[2][0].record()
+    ctx.flowmap(out=out)
+    if ev is not None:
+        ev[2][1].record()
+
+
+def _event_pairs(n):
+    import torch
+
+    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+
+
+def insitu_measure(ctx, wl, grid_ptr, times, dt, steps, warmup, log, gen_ms=None):
+    """Counting pass (live particles entering every step), warm-up and timed
+    intervals of the in situ form.  Returns the measurement record."""
+    import torch
+
+    N = wl.n_steps
+    dcode = DCODE[dt]
+    tuning = ctx.tuning()
+    out = None
+    # counting pass: live particles entering each step and the particle-steps
+    ctx.seed(wl.stride)
+    out = ctx.flowmap()
+    live_in, psteps_c = [], []
+    st = ctx.stats()
+    p_prev = grid_ptr(0)
+    for c in range(N):
+        p_next = grid_ptr(c + 1)
+        live_in.append(st["n_live"])
+        ctx.advect_ptrs([p_prev, p_next], times[c:c + 2], dcode)
+        st2 = ctx.stats()
+        psteps_c.append(st2["particle_steps"] - st["particle_steps"])
+        st = st2
+        p_prev = p_next
+    psteps = int(st["particle_steps"])
+    n_valid = int(st["n_live"])
+    assert sum(psteps_c) == psteps
+    for _ in range(warmup):
+        run_insitu_interval(ctx, wl.stride, N, grid_ptr, times, dcode, out)
+    torch.cuda.synchronize()
+    per = []
+    t_wall = []
+    for k in range(steps):
+        ev = (_event_pairs(1)[0], _event_pairs(N), _event_pairs(1)[0])
+        t0 = time.perf_counter()
+        run_insitu_interval(ctx, wl.stride, N, grid_ptr, times, dcode, out, ev)
+        torch.cuda.synchronize()
+        t_wall.append(time.perf_counter() - t0)
+        step_ms = np.array([a.elapsed_time(b) for a, b in ev[1]])
+        per.append(dict(seed=ev[0][0].elapsed_time(ev[0][1]), steps=step_ms,
+                        flowmap=ev[2][0].elapsed_time(ev[2][1])))
+        assert ctx.stats()["particle_steps"] == psteps, "particle-step count changed between intervals"
+    interval_ms = np.array([p["seed"] + p["steps"].sum() + p["flowmap"] for p in per])
+    med = int(np.argsort(interval_ms)[len(interval_ms) // 2])
+    # launches of the dominant kernel: steps whose call does not also re-sort
+    R = tuning["rebin_every"]
+    plain = np.array([R == 0 or c == 0 or c % R != 0 for c in range(N)])
+    steps_ms = np.stack([p["steps"] for p in per])            # (intervals, N)
+    launch_ms = float(np.median(steps_ms[:, plain].mean(axis=1)))
+    live_plain = float(np.mean(np.asarray(live_in, dtype=np.float64)[plain]))
+    bpp = insitu_bytes_per_pstep(dt)
+    alg_launch = bpp * live_plain
+    achieved = alg_launch / (launch_ms * 1e-3) / 1e9
+    rec = {
+        "interval_ms_median": float(interval_ms[med]), "interval_ms_all": [round(float(v), 4) for v in interval_ms],
+        "seed_ms": round(per[med]["seed"], 4), "flowmap_ms": round(per[med]["flowmap"], 4),
+        "steps_ms": round(float(per[med]["steps"].sum()), 4),
+        "wall_s_per_interval_incl_generation": round(float(np.median(t_wall)), 3),
+        "particle_steps": psteps, "valid_at_end": n_valid, "live_in": live_in,
+        "launch_ms": launch_ms, "launches": int(plain.sum()), "live_per_launch": live_plain,
+        "bytes_per_pstep": bpp, "alg_bytes_per_launch": alg_launch, "achieved_GBs": achieved,
+        "rebin_step_extra_ms": (round(float(np.median(steps_ms[:, ~plain].mean(axis=1))) - launch_ms, 4)
+                                if (~plain).any() else None),
+        "tuning": tuning,
+    }
+    log(f"{wl.name} {dt} in situ: {psteps / (interval_ms[med] * 1e-3):.3e} particle-steps/s, interval "
+        f"{interval_ms[med]:.2f} ms (steps {rec['steps_ms']:.2f}), launch {launch_ms * 1e3:.1f} us, "
+        f"{achieved:.0f} GB/s at {bpp} B per particle-step")
+    return rec
+
+
+def traffic_record(workload: str, dt: str, form: str):
+    """Counter traffic per launch of the dominant kernel (profiles/), while the
+    kernel sources still hash to the value recorded with the counters."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{workload}_{dt}_{form}.json")
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f))
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec
+
+
+def roofline_of(m, dt, workload, form, kernel, copy_gbs):
+    traffic = traffic_record(workload, dt, form)
+    roof = {"bound": "hbm", "achieved": round(m["achieved_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(m["achieved_GBs"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "kernel": kernel, "bytes_per_particle_step": m["bytes_per_pstep"],
+            "particle_steps_per_launch": round(m["live_per_launch"], 1),
+            "algorithmic_bytes_per_launch": int(m["alg_bytes_per_launch"]),
+            "avg_launch_ms": round(m["launch_ms"], 5), "launches_averaged": m["launches"],
+            "device_copy_GBs": round(copy_gbs, 1)}
+    if traffic:
+        roof["traffic_GBs"] = round(traffic["bytes_per_launch"] / (m["launch_ms"] * 1e-3) / 1e9, 1)
+        roof["traffic_source"] = traffic.get("source")
+    return roof
+
+
+def turb_storage_legs(log, copy_gbs, steps=3, warmup=1):
+    """The 256^3 precision workload (64-mode turbulence, 128^3 seeds, 50-step
+    interval) in FP32, FP16 and BF16 storage: the in situ form (one call per
+    cycle, two levels per step) with its roofline at the per-unit figure of
+    that form, and the same interval with all 51 grids resident in fused
+    launches (the one-level model, a footnote)."""
+    import torch
+    from bto_inputs import _turb
+    from bto_inputs.workloads import WORKLOADS
+    from paper_2004_02003_amd import Context
+
+    wl = WORKLOADS["turb_256"]
+    s = wl.make_field()
+    gen = _turb.DeviceTurbulence(s.lazy)
+    times = np.asarray(s.times, dtype=np.float64)
+    shape = (wl.n[2], wl.n[1], wl.n[0], 3)
+    out = {}
+    for dt in ("f32", "f16", "bf16"):
+        dev = [gen.fill(c, dt, torch.empty(shape, dtype=getattr(torch, TDT[dt]), device="cuda"))
+               for c in range(wl.n_cycles)]
+        ptrs = [g.data_ptr() for g in dev]
+        with Context(wl.n, wl.n_seeds) as ctx:
+            ctx.set_tuning(**insitu_shape(wl.name, dt))
+            m = insitu_measure(ctx, wl, lambda c: ptrs[c], times, dt, steps, warmup, log)
+            rec = {"value": round(m["particle_steps"] / (m["interval_ms_median"] * 1e-3), 1),
+                   "interval_ms": round(m["interval_ms_median"], 4), "particle_steps": m["particle_steps"],
+                   "valid_at_end": m["valid_at_end"],
+                   "roofline": roofline_of(m, dt, wl.name, "insitu",
+                                           f"tile_gather_kernel<{dt},linear> + tile_list_kernel (one step per call)",
+                                           copy_gbs),
+                   "tuning": m["tuning"]}
+            # fused: all grids resident, several steps per launch
+            ctx.set_tuning(**fused_shape(wl.name, dt))
+            ts = []
+            for r in range(warmup + steps):
+                ctx.seed(wl.stride)
+                e0, e1 = _event_pairs(1)[0]
+                e0.record()
+                ctx.advect_ptrs(ptrs, times, DCODE[dt])
+                e1.record()
+                torch.cuda.synchronize()
+                if r >= warmup:
+                    ts.append(e0.elapsed_time(e1))
+            ps = ctx.stats()["particle_steps"]
+            rec["fused_all_resident"] = {"value": round(ps / (np.median(ts) * 1e-3), 1),
+                                         "advect_ms": round(float(np.median(ts)), 4), "tuning": ctx.tuning(),
+                                         "one_level_model_bytes_per_particle_step": 8 * field_bytes_per_point(dt)}
+        out[dt] = rec
+        log(f"turb_256 {dt}: in situ {rec['value']:.3e}, fused {rec['fused_all_resident']['value']:.3e} "
+            f"particle-steps/s")
+        del dev
+        torch.cuda.empty_cache()
+    return out
+
+
+# Launch shape per workload and storage (results do not depend on it).
+# In situ (one step per call) the turbulent blocks keep their particles in
+# the tile layout, sorted by 12^3-cell tile and run in Morton tile order (the
+# particles mix at 1.5 cells per step; the tile order keeps the grid lines a
+# tile's particles read in L2 for its neighbours).  Fused (all grids
+# resident, several steps per launch) they re-sort every few steps, and for
+# FP32 grids two lanes per particle halve the cache lines a row load touches.
+INSITU_SHAPE = {
+    "turb_256": dict(tiles=2),
+    "turb_512": dict(tiles=2),
+}
+FUSED_SHAPE = {
+    "turb_256": dict(rebin_every=5),
+    "turb_512": dict(rebin_every=10),
+}
+
+
+def insitu_shape(name, dt):
+    return dict(INSITU_SHAPE.get(name, {}))
+
+
+def fused_shape(name, dt):
+    d = dict(FUSED_SHAPE.get(name, {}))
+    if dt == "f32" and name.startswith("turb"):
+        d["lanes_per_particle"] = 2
+    return d
+
+
+def abc_128_leg(log, copy_gbs, steps=5, warmup=1):
+    """The 128^3 ABC block (FP32, 64^3 seeds, 100-step interval), whose two
+    grid levels fit the Infinity Cache (an effective-bandwidth figure, not an
+    HBM one): all grids resident in fused launches (the fast form when cycles
+    are resident), and the in situ form, one call per cycle."""
+    import torch
+    from bto_inputs.workloads import WORKLOADS
+    from paper_2004_02003_amd import Context, grid_to_device
+
+    wl = WORKLOADS["abc_128"]
+    s = wl.make_field()
+    dev = [grid_to_device(g, "f32") for g in s.grids("f32")]
+    ptrs = [g.data_ptr() for g in dev]
+    times = np.asarray(s.times, dtype=np.float64)
+    out = {}
+    with Context(wl.n, wl.n_seeds) as ctx:
+        tuning = ctx.tuning()
+        ts = []
+        for r in range(warmup + steps):
+            ctx.seed(wl.stride)
+            e0, e1 = _event_pairs(1)[0]
+            e0.record()
+            ctx.advect_ptrs(ptrs, times, DCODE["f32"])
+            e1.record()
+            torch.cuda.synchronize()
+            if r >= warmup:
+                ts.append(e0.elapsed_time(e1))
+        ps = ctx.stats()["particle_steps"]
+        plan = launch_plan(wl.n_steps, tuning["steps_per_launch"], tuning["rebin_every"])
+        out["fused_all_resident"] = {"value": round(ps / (np.median(ts) * 1e-3), 1),
+                                     "advect_ms": round(float(np.median(ts)), 4), "launches": len(plan),
+                                     "particle_steps": int(ps), "tuning": tuning}
+        m = insitu_measure(ctx, wl, lambda c: ptrs[c], times, "f32", steps, warmup, log)
+        out["insitu"] = {"value": round(m["particle_steps"] / (m["interval_ms_median"] * 1e-3), 1),
+                         "interval_ms": round(m["interval_ms_median"], 4),
+                         "roofline_effective": roofline_of(m, "f32", wl.name, "insitu", "advect<f32,linear>",
+                                                           copy_gbs)}
+    log(f"abc_128: fused {out['fused_all_resident']['value']:.3e}, in situ {out['insitu']['value']:.3e}")
+    del dev
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_of(wl, series, dt, turb, grids_host, log, target_s=10.0):
+    """The FP64 oracle, as it stands, on a bounded seed sample of the workload,
+    on all host cores and on one; particle-steps counted as on the GPU."""
+    import oracle
+
+    P = wl.n_seeds
+    every = 1 if not turb else (4096 if wl.n[0] >= 512 else 1024)
+    ids = np.arange(0, P, every)
+    seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
+    N = wl.n_steps
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    F = oracle.Field(wl.n, grids_host, dtype=dt) if not turb else oracle.Field.lazy_turbulence(series, dt)
+    log(f"oracle CPU baseline on {len(ids)} seeds, {threads} threads")
+    tc, reps, ps = 0.0, 0, 0
+    while tc < target_s and reps < 50:
+        t1 = time.perf_counter()
+        o = oracle.flowmap(F, series.times, seeds, N, nthreads=threads)
+        tc += time.perf_counter() - t1
+        ps += int(np.where(o["flag"] == 0, N, o["exit"] + 1).sum())
+        reps += 1
+        if tc > 30.0:
+            break
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu_model)
+    except OSError:
+        pass
+    field_note = ("grid values evaluated on demand from the field's modes and rounded to the storage type"
+                  if turb else "dense grids")
+    res = {"value": round(ps / tc, 1), "unit": "particle-RK4-steps/s", "cores": threads, "kind": "oracle",
+           "cpu": cpu_model, "nproc": os.cpu_count(),
+           "sample": f"{'all' if every == 1 else f'every {every}th'} seed(s) of {wl.name} ({len(ids)} seeds x {N} "
+                     f"steps, {dt} storage, {field_note}) x {reps} repeats, {ps} particle-steps in {tc:.1f} s, "
+                     f"FP64, OpenMP"}
+    ids1 = ids[::16]
+    t1 = time.perf_counter()
+    o1 = oracle.flowmap(F, series.times, seeds[::16], N, nthreads=1)
+    t1 = time.perf_counter() - t1
+    ps1 = int(np.where(o1["flag"] == 0, N, o1["exit"] + 1).sum())
+    one = {"value": round(ps1 / t1, 1), "unit": "particle-RK4-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{len(ids1)} seeds x {N} steps, {ps1} particle-steps in {t1:.1f} s, FP64"}
+    return res, one
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="abc_128")
-    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--steps", type=int, default=5, help="timed intervals (median reported)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="turb_512", choices=("turb_512", "turb_256"))
+    ap.add_argument("--dtype", default=None, help="storage type (default: f16 for turb_512, f32 for turb_256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--steps-per-launch", type=int, default=None,
-                    help="RK4 steps fused into one advection launch (1..128; sets BTO_STEPS_PER_LAUNCH)")
+    ap.add_argument("--no-variants", action="store_true", help="headline only (no legs)")
     ap.add_argument("--rebin-every", type=int, default=None,
                     help="re-sort live particles every this many steps (0 = never; default per workload)")
     ap.add_argument("--lanes-per-particle", type=int, default=None, choices=(1, 2),
                     help="FP32 grids: lanes per particle (default per workload)")
+    ap.add_argument("--tiles", type=int, default=None, choices=(0, 1, 2),
+                    help="particle layout: 0 segments, 1 LDS-staged tiles, 2 tiles (default per workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--leg", action="append", choices=sorted(LEGS),
                     help="run only these legs (repeatable) and print their results as one JSON line")
     args = ap.parse_args(argv)
-    if args.steps_per_launch is not None:
-        os.environ["BTO_STEPS_PER_LAUNCH"] = str(args.steps_per_launch)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the per-block BTO path has no cross-GPU work "
               "(blocks are independent); run one process per block instead.", file=sys.stderr)
@@ -495,254 +818,82 @@ def main(argv=None):
 
         _lib.load()
         assert torch.cuda.is_available(), "bench.py needs a HIP device"
-        print(json.dumps({name: LEGS[name](log) for name in args.leg}), flush=True)
+        copy_gbs = device_copy_rate()
+        print(json.dumps({name: LEGS[name](log, copy_gbs) for name in args.leg}), flush=True)
         return
 
     import torch
-    import oracle
+    from bto_inputs import _turb
     from bto_inputs.workloads import WORKLOADS
-    from paper_2004_02003_amd import Context, grid_to_device
+    from paper_2004_02003_amd import Context
     from paper_2004_02003_amd import _lib
 
     _lib.load()
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     wl = WORKLOADS[args.workload]
-    dt = args.dtype
-    log(f"workload {wl.name}: generating {wl.n_cycles} grids {wl.n} ({dt})")
-    t0 = time.time()
+    dt = args.dtype or ("f16" if wl.name == "turb_512" else "f32")
     series = wl.make_field()
-    turb = series.lazy is not None
-    if turb:
-        # large turbulence blocks: grids generated on the device (bit-identical to the host evaluator)
-        from bto_inputs import _turb
-        gen = _turb.DeviceTurbulence(series.lazy)
-        tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dt]
-        shape = (wl.n[2], wl.n[1], wl.n[0], 3)
-        dev = [gen.fill(c, dt, torch.empty(shape, dtype=tdt, device="cuda")) for c in range(wl.n_cycles)]
-        grids_host = None
-        args.no_variants = True
-    else:
-        grids_host = series.grids(dt) if (not args.no_cpu_baseline or not args.no_variants) else None
-        dev = [grid_to_device(g, dt) for g in (grids_host if grids_host is not None else series.grids(dt))]
-    torch.cuda.synchronize()
-    log(f"grids resident ({sum(g.numel() * g.element_size() for g in dev) / 2**30:.2f} GiB) in {time.time() - t0:.1f}s")
+    gen = _turb.DeviceTurbulence(series.lazy)
     times = np.asarray(series.times, dtype=np.float64)
-    N = wl.n_steps
-    ptrs = [g.data_ptr() for g in dev]
-    dcode = {"f32": _lib.BTO_F32, "f16": _lib.BTO_F16, "bf16": _lib.BTO_BF16}[dt]
+    ring = Ring(gen, wl.n, dt)
+    # generation time of one grid (excluded from the timed region)
+    e0, e1 = _event_pairs(1)[0]
+    ring.ptr(0)
+    e0.record()
+    ring.ptr(1)
+    e1.record()
+    torch.cuda.synchronize()
+    gen_ms = e0.elapsed_time(e1)
+    log(f"workload {wl.name} ({dt}): two-slot ring of {2 * ring.slots[0].numel() * ring.slots[0].element_size() / 2**30:.2f} "
+        f"GiB, one grid generated in {gen_ms:.2f} ms")
 
     ctx = Context(wl.n, wl.n_seeds)
-    tune = dict(LAUNCH_SHAPE.get(wl.name, {}))
+    tune = insitu_shape(wl.name, dt)
     if args.rebin_every is not None:
         tune["rebin_every"] = args.rebin_every
     if args.lanes_per_particle is not None:
         tune["lanes_per_particle"] = args.lanes_per_particle
+    if args.tiles is not None:
+        tune["tiles"] = args.tiles
     if tune:
         ctx.set_tuning(**tune)
-    tuning = ctx.tuning()
-    P = ctx.seed(wl.stride)
-    out = ctx.flowmap()
-
-    # per-launch live counts and particle-steps (untimed pass, one call per launch)
-    plan = launch_plan(N, tuning["steps_per_launch"], tuning["rebin_every"])
-    per_launch = []
-    q = 0
-    ctx.seed(wl.stride)
-    prev = ctx.stats()
-    for K in plan:
-        ctx.advect_ptrs(ptrs[q:q + K + 1], times[q:q + K + 1], dcode)
-        st = ctx.stats()
-        per_launch.append((prev["n_live"], st["particle_steps"] - prev["particle_steps"]))
-        prev = st
-        q += K
-    psteps_interval = prev["particle_steps"]
-    n_valid = prev["n_live"]
-    log(f"{P} seeds, {psteps_interval} particle-steps per interval, {n_valid} valid at the end, "
-        f"{len(plan)} launches of {plan} steps")
-
-    def one_step(ev=None):
-        ctx.seed(wl.stride)
-        if ev is not None:
-            ev[0].record()
-        ctx.advect_ptrs(ptrs, times, dcode)
-        if ev is not None:
-            ev[1].record()
-        ctx.flowmap(out=out)
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        one_step(evs[k])
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    adv_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    st = ctx.stats()
-    assert st["particle_steps"] == psteps_interval, "particle-step count changed between intervals"
-    ms_per_step = 1e3 * t_total / args.steps
-    value = psteps_interval * args.steps / t_total
-    launch_ms = adv_ms / len(plan)
-    bytes_interval = algorithmic_bytes(per_launch, dt, wl.stride)
-    achieved = bytes_interval / len(plan) / (launch_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        rec = json.load(open(TRAFFIC_FILE))
-        if rec.get("kernel_hash") == kernel_hash() and rec.get("workload") == wl.name and rec.get("dtype") == dt:
-            traffic = rec.get("bytes_per_launch")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"advect_kernel<{dt},linear>", "launches_per_step": len(plan),
-            "avg_launch_ms": round(launch_ms, 4),
-            "algorithmic_bytes_per_launch": int(bytes_interval / len(plan))}
-    # context for the peak: what a plain 1 GiB device-to-device copy reaches on this GPU
+    m = insitu_measure(ctx, wl, ring.ptr, times, dt, args.steps, args.warmup, log)
+    ctx.close()
+    del ring
+    torch.cuda.empty_cache()
+    value = m["particle_steps"] / (m["interval_ms_median"] * 1e-3)
     copy_gbs = device_copy_rate()
-    roof["device_copy_GBs"] = round(copy_gbs, 1)
-    if traffic:
-        roof["traffic_GBs"] = round(traffic / (launch_ms * 1e-3) / 1e9, 1)
-    log(f"{value:.3e} particle-steps/s, {ms_per_step:.3f} ms per interval, advect {adv_ms:.3f} ms, "
-        f"{achieved:.0f} GB/s algorithmic")
-
+    kname = (f"tile_gather_kernel<{dt},linear> + tile_list_kernel (one step per call)" if m["tuning"].get("tiles")
+             else f"advect_kernel<{dt},linear> (one step per call)")
+    roof = roofline_of(m, dt, wl.name, "insitu", kname, copy_gbs)
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "particle-RK4-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(m["interval_ms_median"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
-        "data": ("synthetic (seeded analytic ABC flow + Gaussian noise; no dataset)" if not turb else
-                 "synthetic (seeded divergence-free Fourier-mode turbulence; no dataset)"),
+        "data": "synthetic (seeded divergence-free Fourier-mode turbulence generated on the device; no dataset)",
         "config": {"workload": wl.name, "n": list(wl.n), "cycles": wl.n_cycles, "dt": wl.dt,
-                   "stride": wl.stride, "seeds": P, "interval_steps": N, "storage": dt,
-                   "particle_steps_per_interval": int(psteps_interval), "valid_at_end": int(n_valid),
-                   "tuning": tuning},
-        "advect_only": {"value": round(psteps_interval / (adv_ms * 1e-3), 1), "ms": round(adv_ms, 4)},
+                   "stride": wl.stride, "seeds": wl.n_seeds, "interval_steps": wl.n_steps, "storage": dt,
+                   "arithmetic": "fp32 sampling, fp64 positions", "resident_grids": 2,
+                   "form": "one advect call per cycle (in situ)",
+                   "particle_steps_per_interval": m["particle_steps"], "valid_at_end": m["valid_at_end"],
+                   "tuning": m["tuning"]},
+        "timing": {"interval_ms_all": m["interval_ms_all"], "seed_ms": m["seed_ms"], "steps_ms": m["steps_ms"],
+                   "flowmap_ms": m["flowmap_ms"], "rebin_step_extra_ms": m["rebin_step_extra_ms"],
+                   "grid_generation_ms_per_cycle": round(gen_ms, 3),
+                   "wall_s_per_interval_incl_generation": m["wall_s_per_interval_incl_generation"],
+                   "how": "median over the timed intervals of HIP-event times (seed + every step + flow-map "
+                          "write) on the stream the kernels run on; grid generation is excluded"},
         "roofline": roof,
     }
-
-    # in situ form: one call per cycle with the two resident grids
     if not args.no_variants:
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
-        for r in range(4):
-            ctx.seed(wl.stride)
-            if r >= 1:
-                ev[r - 1][0].record()
-            for s_ in range(N):
-                ctx.advect_ptrs(ptrs[s_:s_ + 2], times[s_:s_ + 2], dcode)
-            if r >= 1:
-                ev[r - 1][1].record()
-        torch.cuda.synchronize()
-        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-        # the same one-step launches enqueued by the library in one call (no Python per cycle)
-        ctx.set_tuning(steps_per_launch=1)
-        ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
-        for r in range(4):
-            ctx.seed(wl.stride)
-            if r >= 1:
-                ev2[r - 1][0].record()
-            ctx.advect_ptrs(ptrs, times, dcode)
-            if r >= 1:
-                ev2[r - 1][1].record()
-        torch.cuda.synchronize()
-        ctx.set_tuning(**tuning)
-        ms2 = float(np.mean([a.elapsed_time(b) for a, b in ev2]))
-        result["insitu_per_cycle"] = {"value": round(psteps_interval / (ms * 1e-3), 1), "ms": round(ms, 4),
-                                      "launches": N, "note": "one Python call per cycle",
-                                      "library_enqueued": {"value": round(psteps_interval / (ms2 * 1e-3), 1),
-                                                           "ms": round(ms2, 4)}}
-
-    ctx.close()
-
-    # FP16 / BF16 storage of the same field, with the error against the FP64 oracle
-    if not args.no_variants:
-        variants = {}
-        ids = np.arange(0, P, 97)
-        seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
-        log("oracle on the FP64 grids for the error statement")
-        g64 = [series.make(c) for c in range(series.n_cycles)]
-        o64 = oracle.flowmap(oracle.Field(wl.n, g64), times, seeds, N)
-        del g64
-        for vdt in ("f32", "f16", "bf16"):
-            gh = series.grids(vdt) if vdt != dt else grids_host
-            dv = [grid_to_device(g, vdt) for g in gh]
-            vptr = [g.data_ptr() for g in dv]
-            vcode = {"f32": _lib.BTO_F32, "f16": _lib.BTO_F16, "bf16": _lib.BTO_BF16}[vdt]
-            with Context(wl.n, wl.n_seeds) as c2:
-                c2.seed(wl.stride)
-                c2.advect_ptrs(vptr, times, vcode)
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                tt = []
-                for r in range(5):
-                    c2.seed(wl.stride)
-                    e0.record()
-                    c2.advect_ptrs(vptr, times, vcode)
-                    e1.record()
-                    torch.cuda.synchronize()
-                    tt.append(e0.elapsed_time(e1))
-                fm = c2.flowmap()
-                stv = c2.stats()
-                torch.cuda.synchronize()
-                end = fm["end"].cpu().numpy()[ids]
-                flag = fm["flag"].cpu().numpy()[ids]
-            both = (flag == 0) & (o64["flag"] == 0)
-            err = np.linalg.norm(end[both] - o64["end"][both], axis=1)
-            variants[vdt] = {
-                "advect_value": round(stv["particle_steps"] / (np.median(tt) * 1e-3), 1),
-                "advect_ms": round(float(np.median(tt)), 4),
-                "err_vs_fp64_cells": {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)),
-                                      "max": float(err.max()), "n": int(both.sum()),
-                                      "flag_disagree": int((flag != o64["flag"]).sum())}}
-            del dv
-            torch.cuda.empty_cache()
-        result["storage_variants"] = variants
-
-    if not args.no_variants and wl.name == "abc_128":
-        result["paper_context"] = paper_context(log)
-        result["posthoc_accuracy"] = posthoc_accuracy(log)
-        result["insitu_overlap"] = [insitu_overlap(log, 128, 32), insitu_overlap(log, 256, 64)]
+        result["turb_256_storage"] = turb_storage_legs(log, copy_gbs)
+        result["abc_128"] = abc_128_leg(log, copy_gbs)
+        result["precision_turbulence"] = precision_statement(log, int(os.environ.get("OMP_NUM_THREADS", "0"))
+                                                             or os.cpu_count())
         result["differentiation"] = differentiation(log)
-
+        result["paper_context"] = paper_context(log)
     if not args.no_cpu_baseline:
-        ids = np.arange(0, P, 1 if not turb else 1024)
-        seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        F = oracle.Field(wl.n, grids_host, dtype=dt) if not turb else oracle.Field.lazy_turbulence(series, dt)
-        log(f"oracle CPU baseline on {len(ids)} seeds, {threads} threads")
-        # repeat the sample until about 10 s of CPU work (at most 30 s)
-        tc = 0.0
-        reps = 0
-        ps = 0
-        while tc < 10.0 and reps < 50:
-            t1 = time.perf_counter()
-            o = oracle.flowmap(F, times, seeds, N, nthreads=threads)
-            tc += time.perf_counter() - t1
-            ps += int(np.where(o["flag"] == 0, N, o["exit"] + 1).sum())
-            reps += 1
-            if tc > 30.0:
-                break
-        cpu_model = "unknown"
-        try:
-            with open("/proc/cpuinfo") as fh:
-                cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu_model)
-        except OSError:
-            pass
-        result["cpu_baseline"] = {"value": round(ps / tc, 1), "unit": "particle-RK4-steps/s", "cores": threads,
-                                  "kind": "oracle", "cpu": cpu_model, "nproc": os.cpu_count(),
-                                  "sample": f"{'all' if len(ids) == P else f'every {ids[1] - ids[0]}th'} seed(s) of "
-                                            f"{wl.name} ({len(ids)} seeds x {N} steps) x {reps} repeats, {ps} "
-                                            f"particle-steps in {tc:.1f} s, FP64, OpenMP"}
-        # the same oracle on one thread, on every 16th seed of the same sample
-        ids1 = ids[::16]
-        t1 = time.perf_counter()
-        o1 = oracle.flowmap(F, times, seeds[::16], N, nthreads=1)
-        t1 = time.perf_counter() - t1
-        ps1 = int(np.where(o1["flag"] == 0, N, o1["exit"] + 1).sum())
-        result["cpu_baseline_1thread"] = {"value": round(ps1 / t1, 1), "unit": "particle-RK4-steps/s", "cores": 1,
-                                          "kind": "oracle",
-                                          "sample": f"{len(ids1)} seeds x {N} steps, {ps1} particle-steps in "
-                                                    f"{t1:.1f} s, FP64"}
-        if not args.no_variants and wl.name == "abc_128":
-            result["precision_turbulence"] = precision_statement(log, threads)
+        result["cpu_baseline"], result["cpu_baseline_1thread"] = cpu_baseline_of(wl, series, dt, True, None, log)
 
     if args.copy_probe:
         x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")

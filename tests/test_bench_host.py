@@ -28,25 +28,32 @@ def test_launch_plan_matches_the_library_split(bench):
     assert sum(plan) == 201 and max(plan) - min(plan) <= 1 and max(plan) <= 32
 
 
-def test_algorithmic_bytes_per_unit_figure(bench):
-    # one level over 8 points per particle-step (96 B f32, 48 B f16) plus, per launch,
-    # the first level and 40 B of state per live particle
-    assert bench.algorithmic_bytes([(1000, 25000)], "f32", 2) == 96 * (25000 + 1000) + 40 * 1000
-    assert bench.algorithmic_bytes([(10, 100), (8, 80)], "f16", 2) == 48 * 110 + 400 + 48 * 88 + 320
+def test_insitu_per_unit_figure(bench):
+    # two grid levels over the 8 points of a stride-2 particle's cell, plus 20 B
+    # of state read and 20 B written, per live particle-step
+    assert bench.insitu_bytes_per_pstep("f16") == 136
+    assert bench.insitu_bytes_per_pstep("bf16") == 136
+    assert bench.insitu_bytes_per_pstep("f32") == 232
 
 
 def test_launch_shapes_and_tables_are_consistent(bench):
     from bto_inputs.workloads import WORKLOADS
 
-    assert set(bench.LAUNCH_SHAPE) <= set(WORKLOADS)
-    for shape in bench.LAUNCH_SHAPE.values():
-        assert set(shape) <= {"steps_per_launch", "rebin_every", "blocks_per_cu", "lanes_per_particle"}
+    assert set(bench.INSITU_SHAPE) <= set(WORKLOADS) and set(bench.FUSED_SHAPE) <= set(WORKLOADS)
+    for name in WORKLOADS:
+        for dt in ("f32", "f16", "bf16"):
+            for shape in (bench.insitu_shape(name, dt), bench.fused_shape(name, dt)):
+                assert set(shape) <= {"steps_per_launch", "rebin_every", "blocks_per_cu", "lanes_per_particle",
+                                      "tiles"}
+                assert shape.get("lanes_per_particle", 1) == 1 or dt == "f32"
     assert set(bench.PAPER_ABC_TABLE_MS) == {(i, s) for i in (25, 50, 100) for s in (1, 2, 3)}
     assert set(bench.UNIT_ROUNDOFF) == {"f32", "f16", "bf16"}
     for fn in ("paper_context", "posthoc_accuracy", "insitu_overlap", "precision_statement", "differentiation",
-               "per_cycle", "kernel_hash", "main"):
+               "per_cycle", "kernel_hash", "main", "insitu_measure", "run_insitu_interval", "turb_storage_legs",
+               "abc_128_leg", "cpu_baseline_of", "roofline_of"):
         assert callable(getattr(bench, fn)), fn
-    assert set(bench.LEGS) == {"paper_context", "posthoc_accuracy", "insitu_overlap", "differentiation", "per_cycle"}
+    assert set(bench.LEGS) == {"turb_256_storage", "abc_128", "precision_turbulence", "paper_context",
+                               "posthoc_accuracy", "insitu_overlap", "differentiation", "per_cycle"}
     assert all(callable(f) for f in bench.LEGS.values())
 
 
