@@ -74,10 +74,11 @@ struct bto_ctx {
     TileGeom tg{};
     uint32_t ntiles = 0, tcap = 0;
     int tile_grid = 0;            // workgroups of a tile step (8 x the largest octant of tiles)
-    void* tile_buf = nullptr;     // [order | 3 x ntiles counts | 3 list counts | buckets x 2]
+    void* tile_buf = nullptr;     // [order | slot of tile | 3 x bucket counts, 3 list counts | buckets x 2]
     size_t tile_bytes = 0;
-    int32_t* tile_order = nullptr;
-    uint32_t* tcount = nullptr;
+    int32_t* tile_order = nullptr;  // tile of each bucket (= workgroup)
+    int32_t* tile_slot = nullptr;   // bucket of each tile
+    uint32_t* tcount = nullptr;     // 3 x buckets counts
     uint32_t* lcount = nullptr;
     PState* bpos[2] = {nullptr, nullptr};
     uint32_t* bid[2] = {nullptr, nullptr};
@@ -280,7 +281,7 @@ static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
     uint64_t cap = 2 * per + 32;
     if (cap < 64) cap = 64;
     cap = (cap + 31) & ~(uint64_t)31;
-    if (ntiles * cap > 0xFFFFFFFFull) return fail(c, BTO_ERANGE, "tile buckets exceed 2^32 slots");
+    if ((ntiles + NSEG) * cap > 0xFFFFFFFFull) return fail(c, BTO_ERANGE, "tile buckets exceed 2^32 slots");
     // the same geometry and bucket size as the last interval: everything is in place
     if (c->tile_buf && c->tg.T == tg.T && c->ntiles == (uint32_t)ntiles && c->tcap == (uint32_t)cap) return BTO_OK;
     // workgroup order: all tiles in Morton order, cut into NSEG equal
@@ -302,10 +303,15 @@ static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
         const size_t b = (size_t)ntiles * x / NSEG, e = (size_t)ntiles * (x + 1) / NSEG;
         for (size_t k = b; k < e; ++k) order[(k - b) * NSEG + x] = mt[k].second;
     }
+    // bucket b holds the tile of workgroup b, so there are `grid` buckets
+    std::vector<int32_t> slot_of((size_t)ntiles, -1);
+    for (int b = 0; b < grid; ++b)
+        if (order[(size_t)b] >= 0) slot_of[(size_t)order[(size_t)b]] = b;
     const size_t o_bytes = ((size_t)grid * sizeof(int32_t) + 255) & ~(size_t)255;
-    const size_t c_bytes = ((3 * (size_t)ntiles + 3) * sizeof(uint32_t) + 255) & ~(size_t)255;
-    const size_t b_bytes = (size_t)ntiles * cap * (sizeof(PState) + sizeof(uint32_t));
-    const size_t need = o_bytes + c_bytes + 2 * b_bytes;
+    const size_t s_bytes = ((size_t)ntiles * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t c_bytes = ((3 * (size_t)grid + 3) * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t b_bytes = (size_t)grid * cap * (sizeof(PState) + sizeof(uint32_t));
+    const size_t need = o_bytes + s_bytes + c_bytes + 2 * b_bytes;
     if (need > c->tile_bytes) {
         if (c->tile_buf) {
             hipError_t e = hipStreamSynchronize(s);
@@ -322,15 +328,18 @@ static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
     }
     char* q = static_cast<char*>(c->tile_buf);
     c->tile_order = reinterpret_cast<int32_t*>(q);
-    c->tcount = reinterpret_cast<uint32_t*>(q + o_bytes);
-    c->lcount = c->tcount + 3 * (size_t)ntiles;
-    char* b = q + o_bytes + c_bytes;
+    c->tile_slot = reinterpret_cast<int32_t*>(q + o_bytes);
+    c->tcount = reinterpret_cast<uint32_t*>(q + o_bytes + s_bytes);
+    c->lcount = c->tcount + 3 * (size_t)grid;
+    char* b = q + o_bytes + s_bytes + c_bytes;
     for (int k = 0; k < 2; ++k) {
         c->bpos[k] = reinterpret_cast<PState*>(b + k * b_bytes);
-        c->bid[k] = reinterpret_cast<uint32_t*>(b + k * b_bytes + (size_t)ntiles * cap * sizeof(PState));
+        c->bid[k] = reinterpret_cast<uint32_t*>(b + k * b_bytes + (size_t)grid * cap * sizeof(PState));
     }
     hipError_t e = hipMemcpyAsync(c->tile_order, order.data(), (size_t)grid * sizeof(int32_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // `order` is a host temporary
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->tile_slot, slot_of.data(), (size_t)ntiles * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the tables are host temporaries
     if (e != hipSuccess) return hip_fail(c, e, "tile order upload");
     c->tg = tg;
     c->ntiles = (uint32_t)ntiles;
@@ -344,7 +353,7 @@ static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
 static int tile_enter(bto_ctx* c, int dtype, int max_seg_blocks, hipStream_t s) {
     int rc = tile_setup(c, dtype, s);
     if (rc) return rc;
-    hipError_t e = launch_tile_fill(c->tcount, 3 * (size_t)c->ntiles + 3, s);
+    hipError_t e = launch_tile_fill(c->tcount, 3 * (size_t)c->tile_grid + 3, s);
     if (e != hipSuccess) return hip_fail(c, e, "tile count fill");
     TileBinArgs a{};
     a.g = c->geom;
@@ -355,7 +364,8 @@ static int tile_enter(bto_ctx* c, int dtype, int max_seg_blocks, hipStream_t s) 
     a.id = c->id[c->cur];
     c->tb = 0;
     c->cur = 1 - c->cur;  // the list of the coming step lives in the other particle buffer
-    a.out.tc = c->tcount + (size_t)c->slot * c->ntiles;
+    a.out.tc = c->tcount + (size_t)c->slot * c->tile_grid;
+    a.out.slot_of = c->tile_slot;
     a.out.bpos = c->bpos[c->tb];
     a.out.bid = c->bid[c->tb];
     a.out.cap = c->tcap;
@@ -373,9 +383,9 @@ static int tile_enter(bto_ctx* c, int dtype, int max_seg_blocks, hipStream_t s) 
 static int tile_live(bto_ctx* c, double* out_end, uint8_t* out_flag, int32_t* out_exit, double* ckpt,
                      hipStream_t s) {
     TileLiveArgs a{};
-    a.ntiles = c->ntiles;
+    a.ntiles = (uint32_t)c->tile_grid;
     a.cap = c->tcap;
-    a.tc = c->tcount + (size_t)c->slot * c->ntiles;
+    a.tc = c->tcount + (size_t)c->slot * c->tile_grid;
     a.bpos = c->bpos[c->tb];
     a.bid = c->bid[c->tb];
     a.list_pos = c->pos[c->cur];
@@ -409,11 +419,12 @@ static int tile_step(bto_ctx* c, const void* f0, const void* f1, double h, int d
     a.step0 = c->steps_done;
     a.order = c->tile_order;
     a.order_len = c->tile_grid;
-    a.tc_in = c->tcount + (size_t)sl * c->ntiles;
-    a.tc_clear = c->tcount + (size_t)sl2 * c->ntiles;
+    a.tc_in = c->tcount + (size_t)sl * c->tile_grid;
+    a.tc_clear = c->tcount + (size_t)sl2 * c->tile_grid;
     a.in_pos = c->bpos[c->tb];
     a.in_id = c->bid[c->tb];
-    a.out.tc = c->tcount + (size_t)sl1 * c->ntiles;
+    a.out.tc = c->tcount + (size_t)sl1 * c->tile_grid;
+    a.out.slot_of = c->tile_slot;
     a.out.bpos = c->bpos[1 - c->tb];
     a.out.bid = c->bid[1 - c->tb];
     a.out.cap = c->tcap;

@@ -194,8 +194,9 @@ struct TileGeom {
 };
 
 struct TileOut {
-    uint32_t* tc;       // tile counts of the next step (appended)
-    PState* bpos;       // next step's buckets: ntiles x cap
+    uint32_t* tc;       // bucket counts of the next step (appended)
+    const int32_t* slot_of;  // bucket of each tile id
+    PState* bpos;       // next step's buckets: nbuckets x cap
     uint32_t* bid;
     uint32_t cap;
     PState* list_pos;   // next step's list (bucket overflow)
@@ -210,10 +211,11 @@ struct TileStepArgs {
     Geom g;
     TileGeom tg;
     int32_t step0;            // index of this step in the interval
-    const int32_t* order;     // order[k * NSEG + x]: k-th tile of XCD x's run (-1: none)
-    int32_t order_len;        // entries of order (a multiple of NSEG)
-    const uint32_t* tc_in;    // this step's tile counts
-    uint32_t* tc_clear;       // tile counts cleared for the step after next
+    const int32_t* order;     // tile of bucket b = workgroup b (-1: none); b = k * NSEG + x is the
+                              // k-th tile of XCD x's run
+    int32_t order_len;        // buckets (a multiple of NSEG)
+    const uint32_t* tc_in;    // this step's bucket counts
+    uint32_t* tc_clear;       // bucket counts cleared for the step after next
     const PState* in_pos;     // this step's buckets
     const uint32_t* in_id;
     TileOut out;
@@ -247,7 +249,7 @@ struct TileBinArgs {
 };
 
 struct TileLiveArgs {
-    uint32_t ntiles, cap;
+    uint32_t ntiles, cap;     // buckets, slots per bucket
     const uint32_t* tc;
     const PState* bpos;
     const uint32_t* bid;

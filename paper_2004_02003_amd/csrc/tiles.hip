@@ -21,9 +21,11 @@
 // All sample with the same arithmetic on the same FP32 corner values, so a
 // particle's step does not depend on which kernel took it.
 //
-// Buffers (context-owned): two bucket arrays (ping-pong) of ntiles x cap
-// slots of state + seed id; a ring of three tile-count arrays (the launch
-// pair of a step reads ring slot s, appends to s+1 and clears s+2); the list
+// Buffers (context-owned): two bucket arrays (ping-pong) of nbuckets x cap
+// slots of state + seed id, bucket b holding the tile that workgroup b runs
+// (so a workgroup loads its tile id, particle count and particles at once); a
+// ring of three bucket-count arrays (the launch pair of a step reads ring slot
+// s, appends to s+1 and clears s+2); the list
 // in the context's ping-pong particle buffers with a ring of three counts;
 // per-XCD live and particle-step counters as in the segment layout.
 #include <type_traits>
@@ -45,9 +47,9 @@ __device__ __forceinline__ uint32_t tile_key(const Geom& g, const TileGeom& tg, 
     return t[0] + (uint32_t)tg.nt[0] * (t[1] + (uint32_t)tg.nt[1] * t[2]);
 }
 
-// Write survivors to the bucket of their tile: one returning atomic per
-// (wavefront, destination tile) on the tile's count, lane slots from the
-// ballot.  Slots beyond the bucket's capacity go to the next list instead
+// Write survivors to the bucket of their tile (key: tile id): one returning
+// atomic per (wavefront, destination tile) on the bucket's count, lane slots
+// from the ballot.  Slots beyond the bucket's capacity go to the next list instead
 // (one atomic per wavefront).  Wave-uniform control flow.
 __device__ __forceinline__ void scatter_survivors(bool surv, uint32_t key, const PState& st, uint32_t id,
                                                   const TileOut& o) {
@@ -55,20 +57,28 @@ __device__ __forceinline__ void scatter_survivors(bool surv, uint32_t key, const
     const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long pending = __ballot(surv);
     uint32_t slot = 0;
+    uint32_t bkt = 0;
     while (pending) {
         const int leader = __ffsll((long long)pending) - 1;
         const uint32_t lk = __shfl(key, leader);
         const bool mine = surv && key == lk;
         const unsigned long long same = __ballot(mine) & pending;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&o.tc[lk], (uint32_t)__popcll(same));
+        uint32_t base = 0, lb = 0;
+        if (lane == leader) {
+            lb = (uint32_t)o.slot_of[lk];
+            base = atomicAdd(&o.tc[lb], (uint32_t)__popcll(same));
+        }
         base = __shfl(base, leader);
-        if (mine) slot = base + (uint32_t)__popcll(same & below);
+        lb = __shfl(lb, leader);
+        if (mine) {
+            slot = base + (uint32_t)__popcll(same & below);
+            bkt = lb;
+        }
         pending &= ~same;
     }
     const bool over = surv && slot >= o.cap;
     if (surv && !over) {
-        const size_t q = (size_t)key * o.cap + slot;
+        const size_t q = (size_t)bkt * o.cap + slot;
         o.bpos[q] = st;
         o.bid[q] = id;
     }
@@ -148,15 +158,31 @@ __device__ __forceinline__ void tile_coords(const Geom& g, const TileGeom& tg, c
     }
 }
 
+// Bucket of each neighbour of tile ts (direction (dx, dy, dz) in -1..1 at
+// index (dz + 1) * 9 + (dy + 1) * 3 + dx + 1; -1 outside the block), looked up
+// by the first 27 threads at the start of a workgroup (in parallel with its
+// other loads).
+__device__ __forceinline__ void neighbour_buckets(const TileGeom& tg, const TileOut& o, const int ts[3], int32_t* s_nb) {
+    if (threadIdx.x < 27) {
+        const int d = (int)threadIdx.x;
+        const int q[3] = {ts[0] + d % 3 - 1, ts[1] + (d / 3) % 3 - 1, ts[2] + d / 9 - 1};
+        int32_t b = -1;
+        if (q[0] >= 0 && q[0] < tg.nt[0] && q[1] >= 0 && q[1] < tg.nt[1] && q[2] >= 0 && q[2] < tg.nt[2])
+            b = o.slot_of[q[0] + tg.nt[0] * (q[1] + tg.nt[1] * q[2])];
+        s_nb[d] = b;
+    }
+}
+
 // Survivors of one workgroup batch into the buckets of the next step.  A
 // survivor ends in its own tile or a neighbour (direction dx, dy, dz in
 // -1..1) unless it jumped further: ranks per direction from LDS atomics, then
 // one global atomic per (batch, destination tile) reserves the slots.
 // Survivors that jumped further take one global atomic each; slots beyond the
-// bucket's capacity go to the next list.  Block-uniform (barriers inside).
+// bucket's capacity go to the next list.  Block-uniform (barriers inside;
+// s_nb from neighbour_buckets, written before the first barrier).
 __device__ __forceinline__ void scatter_block(bool surv, const int ts[3], const int td[3], const PState& st,
                                               uint32_t id, const TileGeom& tg, const TileOut& o, uint32_t* s_hist,
-                                              uint32_t* s_base) {
+                                              uint32_t* s_base, const int32_t* s_nb) {
     int dir = 27;
     if (surv) {
         const int dx = td[0] - ts[0], dy = td[1] - ts[1], dz = td[2] - ts[2];
@@ -169,24 +195,22 @@ __device__ __forceinline__ void scatter_block(bool surv, const int ts[3], const 
     __syncthreads();
     if (threadIdx.x < 27) {
         const uint32_t c = s_hist[threadIdx.x];
-        uint32_t b = 0;
-        if (c) {
-            const int d = (int)threadIdx.x;
-            const uint32_t key = (uint32_t)(ts[0] + d % 3 - 1) +
-                                 (uint32_t)tg.nt[0] * ((uint32_t)(ts[1] + (d / 3) % 3 - 1) +
-                                                       (uint32_t)tg.nt[1] * (uint32_t)(ts[2] + d / 9 - 1));
-            b = atomicAdd(&o.tc[key], c);
-        }
-        s_base[threadIdx.x] = b;
+        s_base[threadIdx.x] = c ? atomicAdd(&o.tc[s_nb[threadIdx.x]], c) : 0u;
     }
     __syncthreads();
     bool over = false;
     if (surv) {
-        const uint32_t key = (uint32_t)td[0] + (uint32_t)tg.nt[0] * ((uint32_t)td[1] + (uint32_t)tg.nt[1] * (uint32_t)td[2]);
-        const uint32_t slot = dir < 27 ? s_base[dir] + rank : atomicAdd(&o.tc[key], 1u);
+        uint32_t bkt, slot;
+        if (dir < 27) {
+            bkt = (uint32_t)s_nb[dir];
+            slot = s_base[dir] + rank;
+        } else {
+            bkt = (uint32_t)o.slot_of[td[0] + tg.nt[0] * (td[1] + tg.nt[1] * td[2])];
+            slot = atomicAdd(&o.tc[bkt], 1u);
+        }
         over = slot >= o.cap;
         if (!over) {
-            const size_t q = (size_t)key * o.cap + slot;
+            const size_t q = (size_t)bkt * o.cap + slot;
             o.bpos[q] = st;
             o.bid[q] = id;
         }
@@ -269,7 +293,7 @@ template <int DT, int MODE, int REC, class CA>
 __device__ __forceinline__ void tile_batch(const TileStepArgs& a, bool alive, const PState& st, uint32_t id,
                                            const int tc[3], const char* V0, const char* V1, CA& A, CA& B,
                                            uint32_t& my_steps, uint32_t& my_surv, uint32_t* s_hist,
-                                           uint32_t* s_base) {
+                                           uint32_t* s_base, const int32_t* s_nb) {
     double x[3] = {0.0, 0.0, 0.0};
     int status = S_DEFER;
     if (alive) {
@@ -288,8 +312,68 @@ __device__ __forceinline__ void tile_batch(const TileStepArgs& a, bool alive, co
     my_surv += surv ? 1u : 0u;
     int td[3] = {0, 0, 0};
     if (surv) tile_coords(a.g, a.tg, x, td);
-    scatter_block(surv, tc, td, surv ? pack(x) : st, id, a.tg, a.out, s_hist, s_base);
+    scatter_block(surv, tc, td, surv ? pack(x) : st, id, a.tg, a.out, s_hist, s_base, s_nb);
     append_list(defer, st, id, a.list_pos, a.list_id, a.list_count);
+}
+
+// Lanes of one batch reordered by the (z, y) row of their cell inside the
+// tile (counting sort in LDS), so that the lanes of a wavefront share grid
+// rows: each row load of the sampler then touches a few cache lines per
+// wavefront instead of one per lane.  Block-uniform.
+constexpr int SORT_ROWS_MAX = 16 * 16;  // rows of the largest tile (T <= 16)
+struct SortLds {
+    uint32_t off[SORT_ROWS_MAX + 64];
+    PState pos[BLOCK];
+    uint32_t id[BLOCK];
+};
+
+__device__ __forceinline__ void sort_rows(const TileGeom& tg, const int tc[3], bool on, PState& st, uint32_t& id,
+                                          SortLds& s) {
+    const int T = tg.T;
+    const int nrow = T * T;  // bin nrow: lanes without a particle, last
+    uint32_t key = (uint32_t)nrow;
+    if (on) {
+        int ly = (int)((st.cell >> 10) & 1023u) - tc[1] * T;
+        int lz = (int)(st.cell >> 20) - tc[2] * T;
+        ly = ly < 0 ? 0 : (ly > T - 1 ? T - 1 : ly);
+        lz = lz < 0 ? 0 : (lz > T - 1 ? T - 1 : lz);
+        key = (uint32_t)(lz * T + ly);
+    }
+    for (int i = threadIdx.x; i <= nrow; i += BLOCK) s.off[i] = 0u;
+    __syncthreads();
+    const uint32_t rank = atomicAdd(&s.off[key], 1u);
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+        // exclusive scan of the nrow + 1 bin counts by one wavefront
+        constexpr int PER = (SORT_ROWS_MAX + WAVE) / WAVE;
+        uint32_t v[PER], sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = threadIdx.x * PER + k;
+            v[k] = i <= nrow ? s.off[i] : 0u;
+            sum += v[k];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o);
+            if ((int)threadIdx.x >= o) incl += u;
+        }
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = threadIdx.x * PER + k;
+            if (i <= nrow) s.off[i] = run;
+            run += v[k];
+        }
+    }
+    __syncthreads();
+    const uint32_t dst = s.off[key] + rank;
+    s.pos[dst] = st;
+    s.id[dst] = id;
+    __syncthreads();
+    st = s.pos[threadIdx.x];
+    id = s.id[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
@@ -300,31 +384,43 @@ template <int DT, int MODE, int REC>
 __global__ __launch_bounds__(BLOCK) void tile_gather_kernel(const TileStepArgs a) {
     __shared__ uint32_t s_red[2 * (BLOCK / WAVE)];
     __shared__ uint32_t s_hist[32], s_base[32];
+    __shared__ int32_t s_nb[32];
+    __shared__ SortLds s_sort;
     if (blockIdx.x == 0 && threadIdx.x < NSEG) a.live_clear[threadIdx.x] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == NSEG) *a.list_clear = 0u;
-    const int32_t t = a.order[blockIdx.x];
+    // bucket b = this workgroup: its tile, count and first particles load at once
+    const uint32_t b = blockIdx.x;
+    const int32_t t = a.order[b];
+    uint32_t cnt = a.tc_in[b];
+    const size_t bin = (size_t)b * a.out.cap;
+    PState st0{};
+    uint32_t id0 = 0;
+    if (threadIdx.x < a.out.cap) {  // in the bucket even when beyond its count
+        st0 = a.in_pos[bin + threadIdx.x];
+        id0 = a.in_id[bin + threadIdx.x];
+    }
     if (t < 0) return;
-    if (threadIdx.x == 0) a.tc_clear[t] = 0u;
-    uint32_t cnt = a.tc_in[t];
+    if (threadIdx.x == 0) a.tc_clear[b] = 0u;
     cnt = cnt < a.out.cap ? cnt : a.out.cap;
     if (cnt == 0) return;
     int tc[3], lo[3], ext[3];
     tile_box(a.g, a.tg, t, tc, lo, ext);
+    neighbour_buckets(a.tg, a.out, tc, s_nb);
+    if (cnt <= BLOCK) sort_rows(a.tg, tc, threadIdx.x < cnt, st0, id0, s_sort);
     const char* V0 = in_global(a.f0);
     const char* V1 = in_global(a.f1);
     uint32_t my_steps = 0, my_surv = 0;
-    const size_t bin = (size_t)t * a.out.cap;
     for (uint32_t bb = 0; bb < cnt; bb += BLOCK) {
         const uint32_t i = bb + threadIdx.x;
         const bool alive = i < cnt;
-        PState st{};
-        uint32_t id = 0;
-        if (alive) {
+        PState st = st0;
+        uint32_t id = id0;
+        if (bb && alive) {
             st = a.in_pos[bin + i];
             id = a.in_id[bin + i];
         }
         CellCache<DT> A, B;
-        tile_batch<DT, MODE, REC>(a, alive, st, id, tc, V0, V1, A, B, my_steps, my_surv, s_hist, s_base);
+        tile_batch<DT, MODE, REC>(a, alive, st, id, tc, V0, V1, A, B, my_steps, my_surv, s_hist, s_base, s_nb);
     }
     add_totals(my_steps, my_surv, a.psteps, a.live_out, s_red);
 }
@@ -340,17 +436,27 @@ __global__ __launch_bounds__(BLOCK) void tile_stage_kernel(const TileStepArgs a)
     extern __shared__ __align__(16) char lds[];
     __shared__ uint32_t s_red[2 * (BLOCK / WAVE)];
     __shared__ uint32_t s_hist[32], s_base[32];
+    __shared__ int32_t s_nb[32];
     using SR = StageRegs<DT, MODE, S>;
     if (blockIdx.x == 0 && threadIdx.x < NSEG) a.live_clear[threadIdx.x] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == NSEG) *a.list_clear = 0u;
-    const int32_t t = a.order[blockIdx.x];
+    const uint32_t b = blockIdx.x;
+    const int32_t t = a.order[b];
+    uint32_t cnt = a.tc_in[b];
+    const size_t bin = (size_t)b * a.out.cap;
+    PState st0{};
+    uint32_t id0 = 0;
+    if (threadIdx.x < a.out.cap) {  // in the bucket even when beyond its count
+        st0 = a.in_pos[bin + threadIdx.x];
+        id0 = a.in_id[bin + threadIdx.x];
+    }
     if (t < 0) return;
-    if (threadIdx.x == 0) a.tc_clear[t] = 0u;
-    uint32_t cnt = a.tc_in[t];
+    if (threadIdx.x == 0) a.tc_clear[b] = 0u;
     cnt = cnt < a.out.cap ? cnt : a.out.cap;
     if (cnt == 0) return;
     int tc[3], lo[3], ext[3];
     tile_box(a.g, a.tg, t, tc, lo, ext);
+    neighbour_buckets(a.tg, a.out, tc, s_nb);
     {
         SR sr;
         sr.load(a.g, in_global(a.f0), in_global(a.f1), lo, ext);
@@ -367,17 +473,17 @@ __global__ __launch_bounds__(BLOCK) void tile_stage_kernel(const TileStepArgs a)
     }
     A.S = B.S = S;
     uint32_t my_steps = 0, my_surv = 0;
-    const size_t bin = (size_t)t * a.out.cap;
     for (uint32_t bb = 0; bb < cnt; bb += BLOCK) {
         const uint32_t i = bb + threadIdx.x;
         const bool alive = i < cnt;
-        PState st{};
-        uint32_t id = 0;
-        if (alive) {
+        PState st = st0;
+        uint32_t id = id0;
+        if (bb && alive) {
             st = a.in_pos[bin + i];
             id = a.in_id[bin + i];
         }
-        tile_batch<DT, MODE, REC>(a, alive, st, id, tc, nullptr, nullptr, A, B, my_steps, my_surv, s_hist, s_base);
+        tile_batch<DT, MODE, REC>(a, alive, st, id, tc, nullptr, nullptr, A, B, my_steps, my_surv, s_hist, s_base,
+                                  s_nb);
     }
     add_totals(my_steps, my_surv, a.psteps, a.live_out, s_red);
 }
@@ -466,7 +572,7 @@ __global__ __launch_bounds__(BLOCK) void tile_live_kernel(const TileLiveArgs a) 
         PState st;
         uint32_t id;
         if (q < total) {
-            const uint32_t t = (uint32_t)(q / a.cap), k = (uint32_t)(q % a.cap);
+            const uint32_t t = (uint32_t)(q / a.cap), k = (uint32_t)(q % a.cap);  // bucket, slot
             const uint32_t c = a.tc[t];
             if (k >= c || k >= a.cap) continue;
             st = a.bpos[q];
