@@ -268,12 +268,12 @@ static uint32_t spread3(uint32_t v) {  // bits of v at every third position
 // close in time on one XCD and share their halo lines in its L2).
 static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
     TileGeom tg{};
-    tg.T = tile_side(dtype, c->tiles == 1);
     tg.H = TILE_H;
     uint64_t ntiles = 1;
     for (int d = 0; d < 3; ++d) {
+        tg.T[d] = tile_side(dtype, c->tiles == 1, d);
         const int cells = c->blk.n[d] - 1;
-        tg.nt[d] = (cells + tg.T - 1) / tg.T;
+        tg.nt[d] = (cells + tg.T[d] - 1) / tg.T[d];
         ntiles *= (uint64_t)tg.nt[d];
     }
     if (ntiles > 0xFFFFFFFFull / 2) return fail(c, BTO_ERANGE, "too many tiles");
@@ -283,7 +283,9 @@ static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
     cap = (cap + 31) & ~(uint64_t)31;
     if ((ntiles + NSEG) * cap > 0xFFFFFFFFull) return fail(c, BTO_ERANGE, "tile buckets exceed 2^32 slots");
     // the same geometry and bucket size as the last interval: everything is in place
-    if (c->tile_buf && c->tg.T == tg.T && c->ntiles == (uint32_t)ntiles && c->tcap == (uint32_t)cap) return BTO_OK;
+    if (c->tile_buf && std::memcmp(&c->tg, &tg, sizeof tg) == 0 && c->ntiles == (uint32_t)ntiles &&
+        c->tcap == (uint32_t)cap)
+        return BTO_OK;
     // workgroup order: all tiles in Morton order, cut into NSEG equal
     // contiguous runs, run x for XCD x; order[k * NSEG + x] = k-th tile of run x
     std::vector<std::pair<uint64_t, int32_t>> mt;
@@ -660,9 +662,9 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     int64_t max_seg = 0;
     for (int x = 0; x < NSEG; ++x) max_seg = c->seg_cap[x] > max_seg ? c->seg_cap[x] : max_seg;
     if (c->tile_on) {
-        if (c->tile_layout && tile_side(dtype, c->tiles == 1) != c->tg.T)
+        if (c->tile_layout && tile_side(dtype, c->tiles == 1, 0) != c->tg.T[0])
             return fail(c, BTO_EINVAL, "this interval's tile layout has %d-cell tiles; storage type %d needs %d",
-                        c->tg.T, dtype, tile_side(dtype, c->tiles == 1));
+                        c->tg.T[0], dtype, tile_side(dtype, c->tiles == 1, 0));
         if (!c->tile_layout) {
             rc = tile_enter(c, dtype, blocks_per_seg(c, max_seg, 4), s);
             if (rc) return rc;

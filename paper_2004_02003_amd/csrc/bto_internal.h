@@ -177,10 +177,14 @@ constexpr int TILE_H = 2;       // halo cells staged around a tile
 constexpr int TILE_S_16 = 17;   // staging box side in points, 16-bit grids (tile of 12 cells)
 constexpr int TILE_S_F32 = 13;  // FP32 grids (tile of 8 cells)
 
-// Tile side in cells: staged tiles are sized so that two workgroups' boxes
-// fit a CU's LDS; gathering tiles take the 16-bit staged size for every type.
-__host__ __device__ constexpr int tile_side(int dtype, int staged) {
-    return (staged && dtype == DT_F32 ? TILE_S_F32 : TILE_S_16) - 1 - 2 * TILE_H;
+// Tile sides in cells.  Staged tiles are cubes sized so that two workgroups'
+// boxes fit a CU's LDS.  Gathering tiles are 12^3-cell cubes for every
+// storage type (216 particles at stride 2; long 48 x 6 x 6 tiles, whose
+// wavefronts share longer grid rows, measured the same).
+constexpr int TILE_GATHER[3] = {12, 12, 12};
+
+__host__ __device__ constexpr int tile_side(int dtype, int staged, int axis) {
+    return staged ? (dtype == DT_F32 ? TILE_S_F32 : TILE_S_16) - 1 - 2 * TILE_H : TILE_GATHER[axis];
 }
 
 struct __attribute__((packed, aligned(2))) Pt16 {
@@ -189,7 +193,8 @@ struct __attribute__((packed, aligned(2))) Pt16 {
 };
 
 struct TileGeom {
-    int32_t T, H;       // tile side and halo (cells)
+    int32_t T[3];       // tile sides (cells)
+    int32_t H;          // halo of a staged tile (cells)
     int32_t nt[3];      // tiles per axis
 };
 

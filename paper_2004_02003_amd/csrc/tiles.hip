@@ -42,7 +42,7 @@ __device__ __forceinline__ uint32_t tile_key(const Geom& g, const TileGeom& tg, 
         int v = (int)floor(x[d]);
         v = v > g.n[d] - 2 ? g.n[d] - 2 : v;
         v = v < 0 ? 0 : v;
-        t[d] = (uint32_t)v / (uint32_t)tg.T;
+        t[d] = (uint32_t)v / (uint32_t)tg.T[d];
     }
     return t[0] + (uint32_t)tg.nt[0] * (t[1] + (uint32_t)tg.nt[1] * t[2]);
 }
@@ -154,7 +154,7 @@ __device__ __forceinline__ void tile_coords(const Geom& g, const TileGeom& tg, c
         int v = (int)floor(x[d]);
         v = v > g.n[d] - 2 ? g.n[d] - 2 : v;
         v = v < 0 ? 0 : v;
-        t[d] = v / tg.T;
+        t[d] = v / tg.T[d];
     }
 }
 
@@ -228,8 +228,8 @@ __device__ __forceinline__ void tile_box(const Geom& g, const TileGeom& tg, int 
     tc[2] = t / (tg.nt[0] * tg.nt[1]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int l = tc[d] * tg.T - tg.H;
-        const int h = tc[d] * tg.T + tg.T + tg.H;
+        const int l = tc[d] * tg.T[d] - tg.H;
+        const int h = tc[d] * tg.T[d] + tg.T[d] + tg.H;
         lo[d] = l < 0 ? 0 : l;
         const int hi = h > g.n[d] - 1 ? g.n[d] - 1 : h;
         ext[d] = hi - lo[d] + 1;
@@ -320,7 +320,7 @@ __device__ __forceinline__ void tile_batch(const TileStepArgs& a, bool alive, co
 // tile (counting sort in LDS), so that the lanes of a wavefront share grid
 // rows: each row load of the sampler then touches a few cache lines per
 // wavefront instead of one per lane.  Block-uniform.
-constexpr int SORT_ROWS_MAX = 16 * 16;  // rows of the largest tile (T <= 16)
+constexpr int SORT_ROWS_MAX = 16 * 16;  // rows of the largest tile (y, z sides <= 16)
 struct SortLds {
     uint32_t off[SORT_ROWS_MAX + 64];
     PState pos[BLOCK];
@@ -329,15 +329,15 @@ struct SortLds {
 
 __device__ __forceinline__ void sort_rows(const TileGeom& tg, const int tc[3], bool on, PState& st, uint32_t& id,
                                           SortLds& s) {
-    const int T = tg.T;
-    const int nrow = T * T;  // bin nrow: lanes without a particle, last
+    const int Ty = tg.T[1], Tz = tg.T[2];
+    const int nrow = Ty * Tz;  // bin nrow: lanes without a particle, last
     uint32_t key = (uint32_t)nrow;
     if (on) {
-        int ly = (int)((st.cell >> 10) & 1023u) - tc[1] * T;
-        int lz = (int)(st.cell >> 20) - tc[2] * T;
-        ly = ly < 0 ? 0 : (ly > T - 1 ? T - 1 : ly);
-        lz = lz < 0 ? 0 : (lz > T - 1 ? T - 1 : lz);
-        key = (uint32_t)(lz * T + ly);
+        int ly = (int)((st.cell >> 10) & 1023u) - tc[1] * Ty;
+        int lz = (int)(st.cell >> 20) - tc[2] * Tz;
+        ly = ly < 0 ? 0 : (ly > Ty - 1 ? Ty - 1 : ly);
+        lz = lz < 0 ? 0 : (lz > Tz - 1 ? Tz - 1 : lz);
+        key = (uint32_t)(lz * Ty + ly);
     }
     for (int i = threadIdx.x; i <= nrow; i += BLOCK) s.off[i] = 0u;
     __syncthreads();
