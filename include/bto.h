@@ -80,6 +80,15 @@ enum { BTO_RECORD_CKPT = 1 << 4 };
 /* Per-seed outcome in the flow map. */
 enum { BTO_VALID = 0, BTO_TERMINATED = 1, BTO_INVALID = 2 };
 
+/* Adjoint only (d_status of bto_adjoint_interval): a seed the recorded forward
+ * called valid but whose recomputed steps leave the block -- possible only
+ * with BTO_RECORD_CKPT when the advection rounded differently from the
+ * adjoint's recomputation (launches cut inside a checkpoint segment, two
+ * lanes per particle, the tile layout).  Its gradient rows are zero and its
+ * grid-gradient records are withdrawn (DROPPED); DROPPED_PARTIAL: some of its
+ * grid contributions had already been added with atomics and stay in. */
+enum { BTO_ADJ_DROPPED = 3, BTO_ADJ_DROPPED_PARTIAL = 4 };
+
 typedef struct {
     int32_t n[3];        /* grid points per axis                    */
     double origin[3];    /* world position of grid point (0,0,0)    */
@@ -245,7 +254,9 @@ int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
  *              are added with FP32 atomics instead, in no fixed order.
  *              Only with n_cot = 1.
  *   d_status (n_seeds bytes, may be NULL): BTO_VALID / BTO_TERMINATED /
- *              BTO_INVALID from the recomputed forward.
+ *              BTO_INVALID from the recomputed forward (or the recorded
+ *              flags), BTO_ADJ_DROPPED / BTO_ADJ_DROPPED_PARTIAL for seeds
+ *              dropped by the adjoint (see there).
  * flags: BTO_TIME_LINEAR or BTO_TIME_FROZEN, optionally | BTO_RECORD_CKPT:
  * then the forward pass is not recomputed; the checkpoints and flags that the
  * interval's advection recorded are used (the grids, times and mode must be
@@ -261,6 +272,36 @@ int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
 int bto_adjoint_interval(bto_ctx *ctx, const void *const *d_fields, const double *times, int32_t n_steps,
                          int32_t dtype, int32_t flags, const float *d_cot_end, int32_t n_cot, float *d_grad_seed,
                          float *const *d_grad_fields, uint8_t *d_status, int32_t ckpt_every, void *stream);
+
+/* The same adjoint one checkpoint segment per call, for intervals whose grids
+ * are not all resident (the in situ form keeps two; a segment needs its
+ * ckpt_every + 1).  The interval must have been advected with
+ * BTO_RECORD_CKPT on every call (checkpoints every ckpt_every steps, as for
+ * bto_adjoint_interval with BTO_RECORD_CKPT).  Segment s covers steps
+ * s*k .. min((s+1)*k, N) - 1 (k the recorded spacing, N the steps advected);
+ * call it for s = nseg - 1 down to 0 (nseg = ceil(N / k)), with
+ *   d_fields / times  the k_s + 1 grids and times of cycles s*k .. s*k + k_s
+ *                     (k_s the segment's steps), device pointers / host;
+ *   d_cot_end         the end cotangents as for bto_adjoint_interval (read by
+ *                     the first call, s = nseg - 1; may be NULL later);
+ *   n_cot             1 or 3, the same on every call;
+ *   d_grad_seed       written by the last call (s = 0; may be NULL before);
+ *   d_grad_fields     NULL, or (n_cot = 1) the k_s + 1 FP32 gradient grids of
+ *                     the segment's cycles, accumulated; the first grid of
+ *                     segment s is the last of segment s - 1, so pass the same
+ *                     buffer for it in both calls;
+ *   d_status          NULL, or n_seeds bytes written by the last call (the
+ *                     recorded flags, BTO_ADJ_DROPPED*).
+ * The context carries the cotangents between the calls (n_seeds x 36 bytes).
+ * Results equal bto_adjoint_interval's with BTO_RECORD_CKPT (for grid
+ * gradients: up to the order in which two segments' sums meet on their
+ * shared grid).  BTO_ESTATE without a complete checkpoint record, or when a
+ * call is out of order (each call must sweep the segment below the previous
+ * one; any advect or seed call ends the sequence); BTO_EINVAL for a segment
+ * index out of range or null pointers that are needed. */
+int bto_adjoint_segment(bto_ctx *ctx, int32_t segment, const void *const *d_fields, const double *times,
+                        int32_t dtype, int32_t flags, const float *d_cot_end, int32_t n_cot, float *d_grad_seed,
+                        float *const *d_grad_fields, uint8_t *d_status, void *stream);
 
 /* Finite-time Lyapunov exponent per seed from row-major 3x3 Jacobians:
  * sigma = ln sqrt(lambda_max(J^T J)) / |T| (d_jac: n x 9 floats, d_out: n floats). */

@@ -20,12 +20,13 @@ BTO_TIME_LINEAR, BTO_TIME_FROZEN = 0, 1
 BTO_RECORD_EXIT = 2
 BTO_RECORD_CKPT = 1 << 4
 BTO_VALID, BTO_TERMINATED, BTO_INVALID = 0, 1, 2
+BTO_ADJ_DROPPED, BTO_ADJ_DROPPED_PARTIAL = 3, 4
 
 EXPORTED = [
     "bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
     "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle",
     "bto_set_tuning", "bto_get_tuning", "bto_exit_points", "bto_place_block", "bto_reconstruct_lattice",
-    "bto_flowmap_error", "bto_flowmap_error_static",
+    "bto_flowmap_error", "bto_flowmap_error_static", "bto_adjoint_segment",
 ]
 
 _ERRNAMES = {BTO_EINVAL: "BTO_EINVAL", BTO_ENOMEM: "BTO_ENOMEM", BTO_EHIP: "BTO_EHIP",
@@ -85,6 +86,7 @@ def load() -> ctypes.CDLL:
     L.bto_flowmap_error_static.argtypes = L.bto_flowmap_error.argtypes
     L.bto_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
     L.bto_adjoint_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
+    L.bto_adjoint_segment.argtypes = [vp, i32, vp, vp, i32, i32, vp, i32, vp, vp, vp, vp]
     L.bto_ftle.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]
     L.bto_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.bto_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]

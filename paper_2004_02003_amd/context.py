@@ -233,6 +233,36 @@ class Context:
             _stream_ptr(stream)))
         return out
 
+    def adjoint_segment(self, segment: int, grids: Sequence[torch.Tensor], times, cot: Optional[torch.Tensor] = None,
+                        n_cot: int = 1, grad_seed: Optional[torch.Tensor] = None, grad_grids=None,
+                        status: Optional[torch.Tensor] = None, mode: str = "linear", stream=None) -> None:
+        """One checkpoint segment of the adjoint of a recorded interval
+        (segments swept from the last down to 0): ``grids``/``times`` are the
+        segment's cycles, ``cot`` (P, n_cot, 3) is read by the first call,
+        ``grad_seed`` (P, n_cot, 3) is written by the call for segment 0."""
+        P = self.n_seeds
+        dt = grids[0].dtype
+        shape = (self.n[2], self.n[1], self.n[0], 3)
+        for g in grids:
+            if g.dtype != dt or tuple(g.shape) != shape or not g.is_contiguous():
+                raise ValueError("grids must share dtype and shape")
+        for t, nm in ((cot, "cot"), (grad_seed, "grad_seed")):
+            if t is not None and (t.dtype != torch.float32 or t.numel() != P * n_cot * 3 or not t.is_contiguous()):
+                raise ValueError(f"{nm} must be a contiguous float32 tensor of P x n_cot x 3")
+        times = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        ptrs = (ctypes.c_void_p * len(grids))(*[g.data_ptr() for g in grids])
+        gptr = None
+        if grad_grids is not None:
+            for g in grad_grids:
+                if g.dtype != torch.float32 or tuple(g.shape) != shape or not g.is_contiguous():
+                    raise ValueError("grad grids must be contiguous float32 tensors shaped like the grids")
+            gptr = (ctypes.c_void_p * len(grad_grids))(*[g.data_ptr() for g in grad_grids])
+        self._check(self.L.bto_adjoint_segment(
+            self._h, int(segment), ptrs, times.ctypes.data, _TORCH_DT[dt], _flags(mode),
+            cot.data_ptr() if cot is not None else None, int(n_cot),
+            grad_seed.data_ptr() if grad_seed is not None else None, gptr,
+            status.data_ptr() if status is not None else None, _stream_ptr(stream)))
+
     def ftle(self, jac: torch.Tensor, T: float, stream=None) -> torch.Tensor:
         """FTLE per seed from (P, 3, 3) float32 Jacobians."""
         jac = jac.contiguous()

@@ -25,8 +25,10 @@ struct StageRec {
 };
 
 // One RK4 step that also records every stage's cell, offsets and sampler
-// gradient.  Mirrors rk4_step (same operations in the same order for the
-// position), returning the same status.
+// gradient.  The stage velocities and positions come from the same sampler
+// calls in the same order as rk4_step (so the step is bit-identical to the
+// forward's and takes the same decisions); the gradient G of each stage is
+// taken separately on the same corner values.  Returns the same status.
 template <int DT, int MODE>
 __device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const char* V1, double h,
                                             Stepper<DT>& st, StageRec& rec) {
@@ -45,20 +47,20 @@ __device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const
         rec.base[s] = c.base;
 #pragma unroll
         for (int d = 0; d < 3; ++d) rec.f[s][d] = c.f[d];
-        float G[3][3];
-        if (MODE == MODE_FROZEN) {
+        float G[3][3], unused[3];
+        if (MODE == MODE_FROZEN || s == 0) {
             ensure<DT>(g, V0, c.base, st.A);
-            trilerp_grad<false>(st.A, st.A, c.f, k[s], G);
-        } else if (s == 0) {
-            ensure<DT>(g, V0, c.base, st.A);
-            trilerp_grad<false>(st.A, st.A, c.f, k[s], G);
+            trilerp(st.A, c.f, k[s]);
+            trilerp_grad<false>(st.A, st.A, c.f, unused, G);
         } else if (s == 3) {
             ensure<DT>(g, V1, c.base, st.B);
-            trilerp_grad<false>(st.B, st.B, c.f, k[s], G);
+            trilerp(st.B, c.f, k[s]);
+            trilerp_grad<false>(st.B, st.B, c.f, unused, G);
         } else {
             ensure<DT>(g, V0, c.base, st.A);
             ensure<DT>(g, V1, c.base, st.B);
-            trilerp_grad<true>(st.A, st.B, c.f, k[s], G);
+            trilerp_mid(st.A, st.B, c.f, k[s]);
+            trilerp_grad<true>(st.A, st.B, c.f, unused, G);
         }
         if (!finite3(k[s])) return S_INVALID;
 #pragma unroll
@@ -181,6 +183,9 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a)
     const size_t CK = (size_t)a.ck_stride;
     double* ck = a.ckpt + (size_t)p * 3;
     double* buf = a.buf + (size_t)p * 3;
+    // grids, steps and gradient grids are given from step f_base on
+    const auto F = [&](int n) { return in_global(a.f[n - a.f_base]); };
+    const auto H = [&](int n) { return a.h[n - a.f_base]; };
 
     Stepper<DT> st;
     stepper_init(st);
@@ -199,42 +204,57 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a)
 #pragma unroll
                 for (int d = 0; d < 3; ++d) ck[CK * (size_t)(n / K) + d] = st.x[d];
             }
-            status = rk4_step_alt<DT, MODE>(a.g, in_global(a.f[n]), in_global(a.f[n + 1]), a.h[n], n, st);
+            status = rk4_step_alt<DT, MODE>(a.g, F(n), F(n + 1), H(n), n, st);
         }
     }
-    if (a.status_out) a.status_out[p] = (uint8_t)status;
+    // a seed dropped by the call of a later segment stays dropped
+    const int prior = a.drop ? (int)a.drop[p] : 0;
+    const bool first = a.sg_first == nseg - 1, last = a.sg_last == 0;
 
     float lam[NCOT][3];
 #pragma unroll
     for (int c = 0; c < NCOT; ++c)
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-            lam[c][d] = status == S_VALID ? a.cot[(p * NCOT + c) * 3 + d] * (float)a.sp[d] : 0.f;
+        for (int d = 0; d < 3; ++d) {
+            const float* src = first ? a.cot : a.lam;
+            lam[c][d] = status == S_VALID && !prior ? src[(p * NCOT + c) * 3 + d] * (first ? (float)a.sp[d] : 1.f)
+                                                    : 0.f;
+        }
 
     GradAcc acc;
     acc.base = NO_CELL;
     acc.level = -1;
     acc.nrec = 0;
-    if (status == S_VALID) {
-        for (int sg = nseg - 1; sg >= 0; --sg) {
+    // A recomputed step that does not stay inside contradicts the forward that
+    // called the seed valid: possible only when the forward was taken by the
+    // advection with other rounding (recorded checkpoints; launches cut inside a
+    // checkpoint segment, two lanes per particle, the tile layout).  Such a seed
+    // is dropped.
+    bool mismatch = false;
+    if (status == S_VALID && !prior) {
+        for (int sg = a.sg_first; sg >= a.sg_last && !mismatch; --sg) {
             const int n0 = sg * K;
             const int n1 = (n0 + K < N) ? n0 + K : N;
             stepper_init(st);
 #pragma unroll
             for (int d = 0; d < 3; ++d) st.x[d] = ck[CK * (size_t)sg + d];
-            for (int n = n0; n < n1; ++n) {
+            for (int n = n0; n < n1 && !mismatch; ++n) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) buf[P3 * (size_t)(n - n0) + d] = st.x[d];
-                if (n + 1 < n1) rk4_step_alt<DT, MODE>(a.g, in_global(a.f[n]), in_global(a.f[n + 1]), a.h[n], n - n0, st);
+                if (n + 1 < n1) mismatch = rk4_step_alt<DT, MODE>(a.g, F(n), F(n + 1), H(n), n - n0, st) != S_VALID;
             }
-            for (int n = n1 - 1; n >= n0; --n) {
+            for (int n = n1 - 1; n >= n0 && !mismatch; --n) {
                 Stepper<DT> sr;
                 stepper_init(sr);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) sr.x[d] = buf[P3 * (size_t)(n - n0) + d];
                 StageRec rec;
-                rk4_step_rec<DT, MODE>(a.g, in_global(a.f[n]), in_global(a.f[n + 1]), a.h[n], sr, rec);
-                const float h = (float)a.h[n];
+                if (rk4_step_rec<DT, MODE>(a.g, F(n), F(n + 1), H(n), sr, rec) != S_VALID) {
+                    mismatch = true;
+                    break;
+                }
+                const float h = (float)H(n);
+                const int lv = n - a.f_base;  // grid level of cycle n in the gradient grids
 #pragma unroll
                 for (int c = 0; c < NCOT; ++c) {
                     float lk[4][3], ly[4][3];
@@ -253,28 +273,59 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a)
                     if (c == 0 && a.grad_f) {
                         if (MODE == MODE_FROZEN) {
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n, rec.base[s], rec.f[s], 1.f, lk[s]);
+                            for (int s = 0; s < 4; ++s) acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, lv, rec.base[s], rec.f[s], 1.f, lk[s]);
                         } else {
                             // level n+1 first (it already holds step n+1's share), then level n
-                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n + 1, rec.base[1], rec.f[1], 0.5f, lk[1]);
-                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n + 1, rec.base[2], rec.f[2], 0.5f, lk[2]);
-                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n + 1, rec.base[3], rec.f[3], 1.f, lk[3]);
-                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n, rec.base[0], rec.f[0], 1.f, lk[0]);
-                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n, rec.base[1], rec.f[1], 0.5f, lk[1]);
-                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, n, rec.base[2], rec.f[2], 0.5f, lk[2]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, lv + 1, rec.base[1], rec.f[1], 0.5f, lk[1]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, lv + 1, rec.base[2], rec.f[2], 0.5f, lk[2]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, lv + 1, rec.base[3], rec.f[3], 1.f, lk[3]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, lv, rec.base[0], rec.f[0], 1.f, lk[0]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, lv, rec.base[1], rec.f[1], 0.5f, lk[1]);
+                            acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, lv, rec.base[2], rec.f[2], 0.5f, lk[2]);
                         }
                     }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) lam[c][d] += ly[0][d] + ly[1][d] + ly[2][d] + ly[3][d];
                 }
             }
-            if (a.grad_f) acc_flush(a.g, a.grad_f, a.grec, (uint32_t)p, acc);  // keep it out of the next recompute
+            if (a.grad_f && !mismatch) acc_flush(a.g, a.grad_f, a.grec, (uint32_t)p, acc);  // keep it out of the next recompute
         }
     }
+    int drop = prior;
+    if (mismatch) {
+        // no gradient from this seed: its pending sums are dropped and this
+        // call's grid records withdrawn; contributions already in the grids
+        // (added with atomics after its record slots ran out, or by the call
+        // of a later segment) cannot be, and the status says so
 #pragma unroll
-    for (int c = 0; c < NCOT; ++c)
+        for (int c = 0; c < NCOT; ++c) lam[c][0] = lam[c][1] = lam[c][2] = 0.f;
+        bool withdrawn = true;
+        if (a.grad_f) {
+            if (a.grec.key) {
+                const uint32_t kept = acc.nrec < a.grec.per_seed ? acc.nrec : a.grec.per_seed;
+                const uint64_t unused = (uint64_t)8 << (a.grec.level_bits + a.grec.cell_bits);  // colour 8
+                for (uint32_t j = 0; j < kept; ++j) a.grec.key[(uint64_t)j * a.grec.P + (uint64_t)p] = unused;
+                withdrawn = acc.nrec <= a.grec.per_seed;
+            } else {
+                withdrawn = false;
+            }
+            withdrawn = withdrawn && first;
+        }
+        drop = withdrawn ? ADJ_DROPPED : ADJ_DROPPED_PARTIAL;
+    }
+    if (a.drop && drop != prior) a.drop[p] = (uint8_t)drop;
+    if (last) {
+        if (a.status_out) a.status_out[p] = (uint8_t)(drop ? drop : status);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) a.grad_seed[(p * NCOT + c) * 3 + d] = lam[c][d] * (float)a.g.inv_sp[d];
+        for (int c = 0; c < NCOT; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a.grad_seed[(p * NCOT + c) * 3 + d] = lam[c][d] * (float)a.g.inv_sp[d];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NCOT; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a.lam[(p * NCOT + c) * 3 + d] = lam[c][d];
+    }
 }
 
 // ---------------------------------------------------------------------------

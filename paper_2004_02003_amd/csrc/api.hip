@@ -63,6 +63,11 @@ struct bto_ctx {
     int64_t ck_slots = 0;
     int ck_k = 0;                 // spacing recorded in this interval (0: nothing advected yet)
     bool ck_ok = false;           // every advect call since the seeding recorded, with spacing ck_k
+    // segment-by-segment adjoint: cotangents carried between the calls, dropped-seed marks
+    void* seg_buf = nullptr;
+    size_t seg_bytes = 0;
+    int seg_next = -1;            // segment the next bto_adjoint_segment call must sweep (-1: none)
+    int seg_ncot = 0;
     // grid-gradient records of the adjoint (sorted reduction), grown on demand
     void* grec_buf = nullptr;
     size_t grec_bytes = 0;
@@ -219,6 +224,7 @@ int bto_destroy(bto_ctx* c) {
     if (c->rebin_buf) (void)hipFree(c->rebin_buf);
     if (c->rebin_temp) (void)hipFree(c->rebin_temp);
     if (c->tile_buf) (void)hipFree(c->tile_buf);
+    if (c->seg_buf) (void)hipFree(c->seg_buf);
     delete c;
     return BTO_OK;
 }
@@ -249,6 +255,7 @@ static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hip
     c->ck_ok = true;
     c->tile_on = c->tiles != 0;
     c->tile_layout = false;
+    c->seg_next = -1;
     return BTO_OK;
 }
 
@@ -642,6 +649,7 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
             return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
     if (!c->seeded) return fail(c, BTO_ESTATE, "advect called before seeding");
     if ((int64_t)c->steps_done + n_steps > META_STEP) return fail(c, BTO_ERANGE, "interval too long");
+    c->seg_next = -1;  // more steps: a segment-by-segment adjoint starts over
     hipStream_t s = (hipStream_t)stream;
     // checkpoint record: complete only if every call of the interval records with one spacing
     if (rec_ck) {
@@ -894,47 +902,28 @@ int bto_stats(bto_ctx* c, bto_stats_t* out, void* stream) {
     return BTO_OK;
 }
 
-int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* times, int32_t n_steps,
-                         int32_t dtype, int32_t flags, const float* d_cot_end, int32_t n_cot, float* d_grad_seed,
-                         float* const* d_grad_fields, uint8_t* d_status, int32_t ckpt_every, void* stream) {
-    int rc = begin(c);
-    if (rc) return rc;
-    if (!d_fields || !times || !d_cot_end || !d_grad_seed) return fail(c, BTO_EINVAL, "null argument");
-    if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
-    if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
-    const int mode = flags & ~BTO_RECORD_CKPT;
-    const bool use_ck = (flags & BTO_RECORD_CKPT) != 0;
-    if (mode != BTO_TIME_LINEAR && mode != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
-    if (n_cot != 1 && n_cot != 3) return fail(c, BTO_EINVAL, "n_cot must be 1 or 3 (got %d)", n_cot);
-    if (d_grad_fields && n_cot != 1) return fail(c, BTO_EINVAL, "grid gradients need n_cot == 1");
-    if (ckpt_every < 1) return fail(c, BTO_EINVAL, "ckpt_every must be >= 1");
-    for (int32_t q = 0; q <= n_steps; ++q) {
-        if (!d_fields[q]) return fail(c, BTO_EINVAL, "field pointer %d is null", q);
-        if (d_grad_fields && !d_grad_fields[q]) return fail(c, BTO_EINVAL, "grad field pointer %d is null", q);
-    }
-    for (int32_t q = 0; q < n_steps; ++q)
-        if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
-            return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
-    if (!c->seeded) return fail(c, BTO_ESTATE, "adjoint called before seeding");
-    if (use_ck) {
-        if (!c->ck_ok || c->ck_k == 0)
-            return fail(c, BTO_ESTATE, "no complete checkpoint record (advect every call of the interval with BTO_RECORD_CKPT)");
-        if (n_steps != c->steps_done)
-            return fail(c, BTO_EINVAL, "n_steps %d differs from the %d steps advected", n_steps, c->steps_done);
-        if (ckpt_every != c->ck_k)
-            return fail(c, BTO_EINVAL, "ckpt_every %d differs from the recorded spacing %d", ckpt_every, c->ck_k);
-    }
-    if (c->n_seeds == 0) return BTO_OK;
-    const int K = ckpt_every < n_steps ? ckpt_every : n_steps;
-    const int nseg = (n_steps + K - 1) / K;
+}  // extern "C"
+
+// The adjoint launch over checkpoint segments sg_first .. sg_last with the
+// grids, steps and gradient grids of steps f_base .. f_base + n_local (arguments
+// validated by the callers).  Checkpoints: recomputed into the scratch (whole
+// interval only) or the ones the advection recorded (use_ck).
+static int adjoint_run(bto_ctx* c, const void* const* d_fields, const double* times, int32_t n_local, int32_t N,
+                       int32_t dtype, int mode, bool use_ck, const float* d_cot_end, int32_t n_cot,
+                       float* d_grad_seed, float* const* d_grad_fields, uint8_t* d_status, int32_t ckpt_every,
+                       int32_t sg_first, int32_t sg_last, int32_t f_base, float* lam, uint8_t* drop,
+                       hipStream_t s) {
+    const int K = ckpt_every < N ? ckpt_every : N;
+    const int nseg = (N + K - 1) / K;
     const size_t P = (size_t)c->n_seeds;
-    const size_t tab = ((size_t)(n_steps + 1) * 2 * sizeof(void*) + (size_t)n_steps * sizeof(double) + 255) & ~(size_t)255;
+    const size_t tab =
+        ((size_t)(n_local + 1) * 2 * sizeof(void*) + (size_t)n_local * sizeof(double) + 255) & ~(size_t)255;
     // checkpoint slots live in the scratch unless they were recorded
     const size_t need = tab + P * 3 * sizeof(double) * ((use_ck ? 0 : (size_t)nseg) + (size_t)K);
-    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
     if (need > c->adj_bytes) {
         if (c->adj_scratch) {
-            hipError_t e = hipStreamSynchronize(s);
+            e = hipStreamSynchronize(s);
             if (e != hipSuccess) return hip_fail(c, e, "adjoint scratch sync");
             (void)hipFree(c->adj_scratch);
             c->adj_scratch = nullptr;
@@ -949,22 +938,22 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
     char* base = static_cast<char*>(c->adj_scratch);
     std::vector<char> host(tab, 0);
     const void** hf = reinterpret_cast<const void**>(host.data());
-    void** hg = reinterpret_cast<void**>(host.data() + (size_t)(n_steps + 1) * sizeof(void*));
-    double* hh = reinterpret_cast<double*>(host.data() + (size_t)(n_steps + 1) * 2 * sizeof(void*));
-    for (int32_t q = 0; q <= n_steps; ++q) {
+    void** hg = reinterpret_cast<void**>(host.data() + (size_t)(n_local + 1) * sizeof(void*));
+    double* hh = reinterpret_cast<double*>(host.data() + (size_t)(n_local + 1) * 2 * sizeof(void*));
+    for (int32_t q = 0; q <= n_local; ++q) {
         hf[q] = d_fields[q];
         hg[q] = d_grad_fields ? (void*)d_grad_fields[q] : nullptr;
     }
-    for (int32_t q = 0; q < n_steps; ++q) hh[q] = times[q + 1] - times[q];
-    hipError_t e = hipMemcpyAsync(base, host.data(), tab, hipMemcpyHostToDevice, s);
+    for (int32_t q = 0; q < n_local; ++q) hh[q] = times[q + 1] - times[q];
+    e = hipMemcpyAsync(base, host.data(), tab, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint tables upload");
     AdjointArgs a{};
     a.f = reinterpret_cast<const char* const*>(base);
-    a.grad_f = d_grad_fields ? reinterpret_cast<float* const*>(base + (size_t)(n_steps + 1) * sizeof(void*)) : nullptr;
-    a.h = reinterpret_cast<const double*>(base + (size_t)(n_steps + 1) * 2 * sizeof(void*));
+    a.grad_f = d_grad_fields ? reinterpret_cast<float* const*>(base + (size_t)(n_local + 1) * sizeof(void*)) : nullptr;
+    a.h = reinterpret_cast<const double*>(base + (size_t)(n_local + 1) * 2 * sizeof(void*));
     a.g = c->geom;
-    a.N = n_steps;
+    a.N = N;
     a.k = K;
     a.ncot = n_cot;
     a.P = (int64_t)P;
@@ -987,6 +976,11 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
         a.rec_meta = nullptr;
     }
     a.status_out = d_status;
+    a.sg_first = sg_first;
+    a.sg_last = sg_last;
+    a.f_base = f_base;
+    a.lam = lam;
+    a.drop = drop;
     // grid gradients: records for the sorted reduction, unless the key does not fit
     a.grec = GradRec{};
     uint64_t* key_out = nullptr;
@@ -997,7 +991,7 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
     uint64_t n_slots = 0;
     bool grads_distinct = true;  // the colour passes store without atomics: one buffer per grid
     if (d_grad_fields) {
-        std::vector<const void*> gp(d_grad_fields, d_grad_fields + n_steps + 1);
+        std::vector<const void*> gp(d_grad_fields, d_grad_fields + n_local + 1);
         std::sort(gp.begin(), gp.end());
         grads_distinct = std::adjacent_find(gp.begin(), gp.end()) == gp.end();
     }
@@ -1011,12 +1005,12 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
         GradRec r{};
         r.P = (uint32_t)P;
         r.cell_bits = bits_for(npts - 1);
-        r.level_bits = bits_for((uint64_t)n_steps);
+        r.level_bits = bits_for((uint64_t)n_local);
         const int kb = r.cell_bits + r.level_bits + 3;
         const uint64_t per = 2 * sizeof(uint64_t) + 2 * sizeof(uint32_t) + 24 * sizeof(float);
         const uint64_t max_slots = ((uint64_t)4 << 30) / per;  // at most ~4 GiB of records
         // about one flush per seed and level when particles keep their cells, plus cell changes
-        uint64_t ps = 2 * (uint64_t)(n_steps + 1) + 2;
+        uint64_t ps = 2 * (uint64_t)(n_local + 1) + 2;
         if (ps * P > max_slots) ps = max_slots / P;
         if (kb + 1 <= 64 && ps >= 1) {
             r.per_seed = (uint32_t)ps;
@@ -1061,6 +1055,118 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
         e = launch_grad_reduce(a.grec, n_slots, key_out, idx_out, bounds, sort_temp, sort_bytes, a.grad_f, c->geom, s);
         if (e != hipSuccess) return hip_fail(c, e, "gradient reduction");
     }
+    return BTO_OK;
+}
+
+extern "C" {
+
+int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* times, int32_t n_steps,
+                         int32_t dtype, int32_t flags, const float* d_cot_end, int32_t n_cot, float* d_grad_seed,
+                         float* const* d_grad_fields, uint8_t* d_status, int32_t ckpt_every, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (!d_fields || !times || !d_cot_end || !d_grad_seed) return fail(c, BTO_EINVAL, "null argument");
+    if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
+    if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
+    const int mode = flags & ~BTO_RECORD_CKPT;
+    const bool use_ck = (flags & BTO_RECORD_CKPT) != 0;
+    if (mode != BTO_TIME_LINEAR && mode != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    if (n_cot != 1 && n_cot != 3) return fail(c, BTO_EINVAL, "n_cot must be 1 or 3 (got %d)", n_cot);
+    if (d_grad_fields && n_cot != 1) return fail(c, BTO_EINVAL, "grid gradients need n_cot == 1");
+    if (ckpt_every < 1) return fail(c, BTO_EINVAL, "ckpt_every must be >= 1");
+    for (int32_t q = 0; q <= n_steps; ++q) {
+        if (!d_fields[q]) return fail(c, BTO_EINVAL, "field pointer %d is null", q);
+        if (d_grad_fields && !d_grad_fields[q]) return fail(c, BTO_EINVAL, "grad field pointer %d is null", q);
+    }
+    for (int32_t q = 0; q < n_steps; ++q)
+        if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
+            return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
+    if (!c->seeded) return fail(c, BTO_ESTATE, "adjoint called before seeding");
+    if (use_ck) {
+        if (!c->ck_ok || c->ck_k == 0)
+            return fail(c, BTO_ESTATE, "no complete checkpoint record (advect every call of the interval with BTO_RECORD_CKPT)");
+        if (n_steps != c->steps_done)
+            return fail(c, BTO_EINVAL, "n_steps %d differs from the %d steps advected", n_steps, c->steps_done);
+        if (ckpt_every != c->ck_k)
+            return fail(c, BTO_EINVAL, "ckpt_every %d differs from the recorded spacing %d", ckpt_every, c->ck_k);
+    }
+    if (c->n_seeds == 0) return BTO_OK;
+    const int K = ckpt_every < n_steps ? ckpt_every : n_steps;
+    const int nseg = (n_steps + K - 1) / K;
+    c->seg_next = -1;  // a whole-interval adjoint ends any segment sequence
+    return adjoint_run(c, d_fields, times, n_steps, n_steps, dtype, mode, use_ck, d_cot_end, n_cot, d_grad_seed,
+                       d_grad_fields, d_status, ckpt_every, nseg - 1, 0, 0, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int bto_adjoint_segment(bto_ctx* c, int32_t segment, const void* const* d_fields, const double* times,
+                        int32_t dtype, int32_t flags, const float* d_cot_end, int32_t n_cot, float* d_grad_seed,
+                        float* const* d_grad_fields, uint8_t* d_status, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (!d_fields || !times) return fail(c, BTO_EINVAL, "null field or time array");
+    if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
+    const int mode = flags & ~BTO_RECORD_CKPT;
+    if (mode != BTO_TIME_LINEAR && mode != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    if (n_cot != 1 && n_cot != 3) return fail(c, BTO_EINVAL, "n_cot must be 1 or 3 (got %d)", n_cot);
+    if (d_grad_fields && n_cot != 1) return fail(c, BTO_EINVAL, "grid gradients need n_cot == 1");
+    if (!c->seeded) return fail(c, BTO_ESTATE, "adjoint called before seeding");
+    if (!c->ck_ok || c->ck_k == 0 || c->steps_done == 0)
+        return fail(c, BTO_ESTATE, "no complete checkpoint record (advect every call of the interval with BTO_RECORD_CKPT)");
+    const int N = c->steps_done;
+    const int K = c->ck_k < N ? c->ck_k : N;
+    const int nseg = (N + K - 1) / K;
+    if (segment < 0 || segment >= nseg) return fail(c, BTO_EINVAL, "segment %d outside 0..%d", segment, nseg - 1);
+    const bool first = segment == nseg - 1;
+    if (first) {
+        if (!d_cot_end) return fail(c, BTO_EINVAL, "the last segment needs the end cotangents");
+    } else if (c->seg_next != segment || c->seg_ncot != n_cot) {
+        return fail(c, BTO_ESTATE, "segments must be swept from %d down to 0 with one n_cot (expected %d)", nseg - 1,
+                    c->seg_next);
+    }
+    if (segment == 0 && !d_grad_seed) return fail(c, BTO_EINVAL, "segment 0 needs the seed-gradient output");
+    const int n0 = segment * K, n1 = n0 + K < N ? n0 + K : N;
+    const int nl = n1 - n0;
+    for (int32_t q = 0; q <= nl; ++q) {
+        if (!d_fields[q]) return fail(c, BTO_EINVAL, "field pointer %d is null", q);
+        if (d_grad_fields && !d_grad_fields[q]) return fail(c, BTO_EINVAL, "grad field pointer %d is null", q);
+    }
+    for (int32_t q = 0; q < nl; ++q)
+        if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
+            return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
+    hipStream_t s = (hipStream_t)stream;
+    if (c->n_seeds == 0) {
+        c->seg_next = segment - 1;
+        c->seg_ncot = n_cot;
+        return BTO_OK;
+    }
+    // cotangents carried between the calls and the dropped-seed marks
+    const size_t lam_bytes = ((size_t)c->n_seeds * 3 * 3 * sizeof(float) + 255) & ~(size_t)255;
+    const size_t need = lam_bytes + (((size_t)c->n_seeds + 3) & ~(size_t)3);
+    if (need > c->seg_bytes) {
+        if (c->seg_buf) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(c, e, "segment state sync");
+            (void)hipFree(c->seg_buf);
+            c->seg_buf = nullptr;
+            c->seg_bytes = 0;
+        }
+        if (hipMalloc(&c->seg_buf, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, BTO_ENOMEM, "segment state of %zu bytes", need);
+        }
+        c->seg_bytes = need;
+    }
+    float* lam = static_cast<float*>(c->seg_buf);
+    uint8_t* drop = reinterpret_cast<uint8_t*>(static_cast<char*>(c->seg_buf) + lam_bytes);
+    if (first) {
+        hipError_t e = launch_tile_fill(reinterpret_cast<uint32_t*>(drop), ((size_t)c->n_seeds + 3) / 4, s);
+        if (e != hipSuccess) return hip_fail(c, e, "segment state clear");
+    }
+    rc = adjoint_run(c, d_fields, times, nl, N, dtype, mode, true, d_cot_end, n_cot, d_grad_seed, d_grad_fields,
+                     d_status, c->ck_k, segment, segment, n0, lam, drop, s);
+    if (rc) return rc;
+    c->seg_next = segment - 1;
+    c->seg_ncot = n_cot;
     return BTO_OK;
 }
 

@@ -31,6 +31,8 @@ enum : int { S_VALID = 0, S_TERMINATED = 1, S_INVALID = 2 };
 // grid values outside the staged box, so the step is left undone (x kept at
 // the step's start) and redone from the global grids.  Never recorded.
 constexpr int S_DEFER = 3;
+// Adjoint statuses of seeds whose recomputation contradicts a recorded forward.
+constexpr int ADJ_DROPPED = 3, ADJ_DROPPED_PARTIAL = 4;
 enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 enum : int { MODE_LINEAR = 0, MODE_FROZEN = 1 };
 // Per-seed record of an ended particle: flag << 28 | bits below | exit step.

@@ -137,6 +137,16 @@ struct AdjointArgs {
     uint8_t* status_out;        // P (may be null): status of the recomputed forward
     const int32_t* rec_meta;    // non-null: take the forward from recorded checkpoints and these records
     GradRec grec;               // grid-gradient records (grec.key null: atomics)
+    // Segments swept by this launch, sg_first down to sg_last (the whole
+    // interval: nseg - 1 .. 0).  f, h and grad_f hold the grids, steps and
+    // gradient grids from step f_base on.  lam (P x ncot x 3, cell units)
+    // carries the cotangents from one launch to the next (read unless sg_first
+    // is the last segment, written unless sg_last is 0); drop (P bytes, may be
+    // null for a single launch) marks seeds dropped by an earlier launch.
+    int32_t sg_first, sg_last;
+    int32_t f_base;
+    float* lam;
+    uint8_t* drop;
 };
 
 // Checkpoint of the live particles for the adjoint: FP64 positions (cell

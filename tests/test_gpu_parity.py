@@ -492,7 +492,7 @@ def test_error_paths_and_tuning_through_the_c_abi():
             ctx.set_tuning(ckpt_every=0)
         assert e.value.code == _lib.BTO_EINVAL and "ckpt_every" in str(e.value)
         with pytest.raises(BTOError) as e:
-            ctx.set_tuning(tiles=2)
+            ctx.set_tuning(tiles=3)
         assert e.value.code == _lib.BTO_EINVAL and "tiles" in str(e.value)
         ctx.set_tuning(steps_per_launch=2, rebin_every=1, blocks_per_cu=1, lanes_per_particle=2, ckpt_every=7)
         assert ctx.tuning() == dict(steps_per_launch=2, rebin_every=1, blocks_per_cu=1, lanes_per_particle=2,
