@@ -282,7 +282,10 @@ def precision_statement(log, threads):
         log(f"precision {name}: FP64 oracle on {len(ids)} seeds in {time.perf_counter() - t0:.1f} s")
         nJ = np.linalg.norm(o["jac"], axis=(1, 2), ord=2)
         res = {}
-        for dt in wl.dtypes:
+        runs = [(dt, dt, False) for dt in wl.dtypes]
+        if "f32" in wl.dtypes:
+            runs.insert(1, ("f32_sampled_fp64", "f32", True))
+        for key, dt, fp64 in runs:
             vmax = 0.0
             ring = Ring(gen, wl.n, dt)
             with Context(wl.n, wl.n_seeds) as ctx:
@@ -293,7 +296,7 @@ def precision_statement(log, threads):
                     p_next = ring.ptr(c + 1)
                     if c % 10 == 0:
                         vmax = max(vmax, float(ring.slots[(c + 1) % 2].float().abs().max()))
-                    ctx.advect_ptrs([p_prev, p_next], s.times[c:c + 2], DCODE[dt])
+                    ctx.advect_ptrs([p_prev, p_next], s.times[c:c + 2], DCODE[dt], fp64=fp64)
                     p_prev = p_next
                 fm = ctx.flowmap()
                 torch.cuda.synchronize()
@@ -303,15 +306,15 @@ def precision_statement(log, threads):
             torch.cuda.empty_cache()
             both = (flag == 0) & (o["flag"] == 0)
             err = np.linalg.norm(end[both] - o["end"][both], axis=1)
-            bound = nJ[both] * N * wl.dt * vmax * np.sqrt(3.0) * (UNIT_ROUNDOFF[dt] + 2.0 ** -21)
+            bound = nJ[both] * N * wl.dt * vmax * np.sqrt(3.0) * (UNIT_ROUNDOFF[dt] + (2.0 ** -50 if fp64 else 2.0 ** -21))
             safe = o["margin"] >= 1e-6
-            res[dt] = {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
+            res[key] = {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
                        "n": int(both.sum()), "beyond_1e-5_pct": round(100.0 * float((err > 1e-5).mean()), 3),
                        "within_first_order_bound_pct": round(100.0 * float((err <= bound).mean()), 2),
                        "bound_median": float(np.median(bound)),
                        "flag_disagree": int((flag != o["flag"]).sum()),
                        "flag_disagree_outside_margin": int(((flag != o["flag"]) & safe).sum())}
-            log(f"precision {name} {dt}: {res[dt]}")
+            log(f"precision {name} {key}: {res[key]}")
         out[name] = {"seeds": f"every {every}th of {wl.n_seeds} ({len(ids)})", "steps": N,
                      "cells": "end-position L2 error, cells", **res}
     return out
@@ -487,7 +490,7 @@ class Ring:
         return self.slots[c % 2].data_ptr()
 
 
-def run_insitu_interval(ctx, stride, N, grid_ptr, times, dcode, out, ev=None):
+def run_insitu_interval(ctx, stride, N, grid_ptr, times, dcode, out, ev=None, fp64=False):
     """seed, N one-step advect calls, flow-map write.  grid_ptr(c) returns the
     device pointer of cycle c's grid (a ring slot, filled on the stream before
     the step that first reads it).  ev: (seed, steps[N], flowmap) event pairs."""
@@ -501,7 +504,7 @@ def run_insitu_interval(ctx, stride, N, grid_ptr, times, dcode, out, ev=None):
         p_next = grid_ptr(c + 1)
         if ev is not None:
             ev[1][c][0].record()
-        ctx.advect_ptrs([p_prev, p_next], times[c:c + 2], dcode)
+        ctx.advect_ptrs([p_prev, p_next], times[c:c + 2], dcode, fp64=fp64)
         if ev is not None:
             ev[1][c][1].record()
         p_prev = p_next
@@ -518,7 +521,7 @@ def _event_pairs(n):
     return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
 
 
-def insitu_measure(ctx, wl, grid_ptr, times, dt, steps, warmup, log, gen_ms=None):
+def insitu_measure(ctx, wl, grid_ptr, times, dt, steps, warmup, log, fp64=False):
     """Counting pass (live particles entering every step), warm-up and timed
     intervals of the in situ form.  Returns the measurement record."""
     import torch
@@ -536,7 +539,7 @@ def insitu_measure(ctx, wl, grid_ptr, times, dt, steps, warmup, log, gen_ms=None
     for c in range(N):
         p_next = grid_ptr(c + 1)
         live_in.append(st["n_live"])
-        ctx.advect_ptrs([p_prev, p_next], times[c:c + 2], dcode)
+        ctx.advect_ptrs([p_prev, p_next], times[c:c + 2], dcode, fp64=fp64)
         st2 = ctx.stats()
         psteps_c.append(st2["particle_steps"] - st["particle_steps"])
         st = st2
@@ -545,14 +548,14 @@ def insitu_measure(ctx, wl, grid_ptr, times, dt, steps, warmup, log, gen_ms=None
     n_valid = int(st["n_live"])
     assert sum(psteps_c) == psteps
     for _ in range(warmup):
-        run_insitu_interval(ctx, wl.stride, N, grid_ptr, times, dcode, out)
+        run_insitu_interval(ctx, wl.stride, N, grid_ptr, times, dcode, out, fp64=fp64)
     torch.cuda.synchronize()
     per = []
     t_wall = []
     for k in range(steps):
         ev = (_event_pairs(1)[0], _event_pairs(N), _event_pairs(1)[0])
         t0 = time.perf_counter()
-        run_insitu_interval(ctx, wl.stride, N, grid_ptr, times, dcode, out, ev)
+        run_insitu_interval(ctx, wl.stride, N, grid_ptr, times, dcode, out, ev, fp64=fp64)
         torch.cuda.synchronize()
         t_wall.append(time.perf_counter() - t0)
         step_ms = np.array([a.elapsed_time(b) for a, b in ev[1]])
@@ -633,13 +636,19 @@ def turb_storage_legs(log, copy_gbs, steps=3, warmup=1):
     times = np.asarray(s.times, dtype=np.float64)
     shape = (wl.n[2], wl.n[1], wl.n[0], 3)
     out = {}
-    for dt in ("f32", "f16", "bf16"):
-        dev = [gen.fill(c, dt, torch.empty(shape, dtype=getattr(torch, TDT[dt]), device="cuda"))
-               for c in range(wl.n_cycles)]
+    dev, dev_dt = None, None
+    for key, dt, fp64 in (("f32", "f32", False), ("f32_sampled_fp64", "f32", True), ("f16", "f16", False),
+                          ("bf16", "bf16", False)):
+        if dev_dt != dt:
+            dev = None
+            torch.cuda.empty_cache()
+            dev = [gen.fill(c, dt, torch.empty(shape, dtype=getattr(torch, TDT[dt]), device="cuda"))
+                   for c in range(wl.n_cycles)]
+            dev_dt = dt
         ptrs = [g.data_ptr() for g in dev]
         with Context(wl.n, wl.n_seeds) as ctx:
             ctx.set_tuning(**insitu_shape(wl.name, dt))
-            m = insitu_measure(ctx, wl, lambda c: ptrs[c], times, dt, steps, warmup, log)
+            m = insitu_measure(ctx, wl, lambda c: ptrs[c], times, dt, steps, warmup, log, fp64=fp64)
             rec = {"value": round(m["particle_steps"] / (m["interval_ms_median"] * 1e-3), 1),
                    "interval_ms": round(m["interval_ms_median"], 4), "particle_steps": m["particle_steps"],
                    "valid_at_end": m["valid_at_end"],
@@ -647,14 +656,15 @@ def turb_storage_legs(log, copy_gbs, steps=3, warmup=1):
                                            f"tile_gather_kernel<{dt},linear> + tile_list_kernel (one step per call)",
                                            copy_gbs),
                    "tuning": m["tuning"]}
-            # fused: all grids resident, several steps per launch
+            # fused: all grids resident, several steps per launch (segment layout,
+            # latched at the next seeding)
             ctx.set_tuning(**fused_shape(wl.name, dt))
             ts = []
             for r in range(warmup + steps):
                 ctx.seed(wl.stride)
                 e0, e1 = _event_pairs(1)[0]
                 e0.record()
-                ctx.advect_ptrs(ptrs, times, DCODE[dt])
+                ctx.advect_ptrs(ptrs, times, DCODE[dt], fp64=fp64)
                 e1.record()
                 torch.cuda.synchronize()
                 if r >= warmup:
@@ -663,11 +673,13 @@ def turb_storage_legs(log, copy_gbs, steps=3, warmup=1):
             rec["fused_all_resident"] = {"value": round(ps / (np.median(ts) * 1e-3), 1),
                                          "advect_ms": round(float(np.median(ts)), 4), "tuning": ctx.tuning(),
                                          "one_level_model_bytes_per_particle_step": 8 * field_bytes_per_point(dt)}
-        out[dt] = rec
-        log(f"turb_256 {dt}: in situ {rec['value']:.3e}, fused {rec['fused_all_resident']['value']:.3e} "
+        if fp64:
+            rec["sampler"] = "fp64 (BTO_SAMPLE_FP64)"
+        out[key] = rec
+        log(f"turb_256 {key}: in situ {rec['value']:.3e}, fused {rec['fused_all_resident']['value']:.3e} "
             f"particle-steps/s")
-        del dev
-        torch.cuda.empty_cache()
+    dev = None
+    torch.cuda.empty_cache()
     return out
 
 
@@ -683,8 +695,8 @@ INSITU_SHAPE = {
     "turb_512": dict(tiles=2),
 }
 FUSED_SHAPE = {
-    "turb_256": dict(rebin_every=5),
-    "turb_512": dict(rebin_every=10),
+    "turb_256": dict(rebin_every=5, tiles=0),
+    "turb_512": dict(rebin_every=10, tiles=0),
 }
 
 

@@ -77,6 +77,14 @@ enum { BTO_RECORD_EXIT = 2 };
  * one ckpt_every). */
 enum { BTO_RECORD_CKPT = 1 << 4 };
 
+/* Flag bit of bto_advect_interval: sample the field in FP64 -- in-cell
+ * offsets, trilinear weights, the weighted sums and the stage velocities --
+ * instead of FP32 (grid values and positions are unchanged: the stored values
+ * and FP64 positions).  Lowers the sampler's rounding below the FP32 grid
+ * values' own, at more ALU work per step; lanes_per_particle 2 does not apply.
+ * The adjoint always samples in FP32 (it rejects the flag). */
+enum { BTO_SAMPLE_FP64 = 1 << 5 };
+
 /* Per-seed outcome in the flow map. */
 enum { BTO_VALID = 0, BTO_TERMINATED = 1, BTO_INVALID = 2 };
 

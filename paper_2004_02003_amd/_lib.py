@@ -19,6 +19,7 @@ BTO_F32, BTO_F16, BTO_BF16 = 0, 1, 2
 BTO_TIME_LINEAR, BTO_TIME_FROZEN = 0, 1
 BTO_RECORD_EXIT = 2
 BTO_RECORD_CKPT = 1 << 4
+BTO_SAMPLE_FP64 = 1 << 5
 BTO_VALID, BTO_TERMINATED, BTO_INVALID = 0, 1, 2
 BTO_ADJ_DROPPED, BTO_ADJ_DROPPED_PARTIAL = 3, 4
 

@@ -20,9 +20,9 @@ _TORCH_DT = {torch.float32: _lib.BTO_F32, torch.float16: _lib.BTO_F16, torch.bfl
 _MODES = {"linear": _lib.BTO_TIME_LINEAR, "frozen": _lib.BTO_TIME_FROZEN}
 
 
-def _flags(mode: str, record_exit: bool = False, record_ckpt: bool = False) -> int:
+def _flags(mode: str, record_exit: bool = False, record_ckpt: bool = False, fp64: bool = False) -> int:
     return (_MODES[mode] | (_lib.BTO_RECORD_EXIT if record_exit else 0)
-            | (_lib.BTO_RECORD_CKPT if record_ckpt else 0))
+            | (_lib.BTO_RECORD_CKPT if record_ckpt else 0) | (_lib.BTO_SAMPLE_FP64 if fp64 else 0))
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -134,11 +134,12 @@ class Context:
         return self.n_seeds
 
     def advect(self, grids: Sequence[torch.Tensor], times, mode: str = "linear", record_exit: bool = False,
-               stream=None, record_ckpt: bool = False):
+               stream=None, record_ckpt: bool = False, fp64: bool = False):
         """n = len(grids) - 1 RK4 steps through the given consecutive cycles;
         ``record_exit`` keeps the exit point of every particle terminated here
         (``exit_points``); ``record_ckpt`` records checkpoints every
-        ``tuning()["ckpt_every"]`` steps for ``adjoint(..., recorded=True)``."""
+        ``tuning()["ckpt_every"]`` steps for ``adjoint(..., recorded=True)``;
+        ``fp64`` samples the field in FP64 (BTO_SAMPLE_FP64)."""
         if len(grids) < 2:
             raise ValueError("need at least two grids (one step)")
         dt = grids[0].dtype
@@ -153,17 +154,17 @@ class Context:
             raise ValueError("one time per grid")
         ptrs = (ctypes.c_void_p * len(grids))(*[g.data_ptr() for g in grids])
         self._check(self.L.bto_advect_interval(self._h, ptrs, times.ctypes.data, len(grids) - 1,
-                                               _TORCH_DT[dt], _flags(mode, record_exit, record_ckpt),
+                                               _TORCH_DT[dt], _flags(mode, record_exit, record_ckpt, fp64),
                                                _stream_ptr(stream)))
         self.steps_advected = getattr(self, "steps_advected", 0) + len(grids) - 1
 
     def advect_ptrs(self, ptrs, times, dtype: int, mode: str = "linear", record_exit: bool = False, stream=None,
-                    record_ckpt: bool = False):
+                    record_ckpt: bool = False, fp64: bool = False):
         """Same as ``advect`` with raw device pointers (no per-call tensor checks)."""
         arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
         t = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
         self._check(self.L.bto_advect_interval(self._h, arr, t.ctypes.data, len(ptrs) - 1, int(dtype),
-                                               _flags(mode, record_exit, record_ckpt), _stream_ptr(stream)))
+                                               _flags(mode, record_exit, record_ckpt, fp64), _stream_ptr(stream)))
         self.steps_advected = getattr(self, "steps_advected", 0) + len(ptrs) - 1
 
     def flowmap(self, with_seeds: bool = True, count_valid: bool = False, out=None, stream=None):

@@ -48,7 +48,7 @@ __device__ __forceinline__ int rk4_step_rec(const Geom& g, const char* V0, const
 #pragma unroll
         for (int d = 0; d < 3; ++d) rec.f[s][d] = c.f[d];
         float G[3][3], unused[3];
-        if (MODE == MODE_FROZEN || s == 0) {
+        if (is_frozen<MODE> || s == 0) {
             ensure<DT>(g, V0, c.base, st.A);
             trilerp(st.A, c.f, k[s]);
             trilerp_grad<false>(st.A, st.A, c.f, unused, G);
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adjoint_kernel(const AdjointArgs a)
                     for (int d = 0; d < 3; ++d) lk[0][d] = (h / 6.f) * lam[c][d] + (0.5f * h) * ly[1][d];
                     gT(rec.G[0], lk[0], ly[0]);
                     if (c == 0 && a.grad_f) {
-                        if (MODE == MODE_FROZEN) {
+                        if (is_frozen<MODE>) {
 #pragma unroll
                             for (int s = 0; s < 4; ++s) acc_add(a.g, a.grad_f, a.grec, (uint32_t)p, acc, lv, rec.base[s], rec.f[s], 1.f, lk[s]);
                         } else {

@@ -56,12 +56,12 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
                 status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], x, A, B, on_exit);
                 if (status != S_VALID) break;
                 A.base = NO_CELL;
-                if (MODE != MODE_LINEAR) B.base = NO_CELL;
+                if (is_frozen<MODE>) B.base = NO_CELL;
                 if (++s >= a.K) break;
                 status = rk4_step<DT, MODE>(a.g, a.f[s], a.f[s + 1], a.h[s], x, B, A, on_exit);
                 if (status != S_VALID) break;
                 B.base = NO_CELL;
-                if (MODE != MODE_LINEAR) A.base = NO_CELL;
+                if (is_frozen<MODE>) A.base = NO_CELL;
             }
             if (owner) my_steps += (status == S_VALID) ? (uint32_t)a.K : (uint32_t)(s + 1);
         }
@@ -116,16 +116,32 @@ struct Variant {
     static constexpr int DT = DT_, MODE = MODE_, LPP = LPP_, REC = REC_;
 };
 
+template <int DT, int LPP, int MODE, class F>
+static auto with_rec(int rec, F&& f) {
+    return rec ? f(Variant<DT, MODE, LPP, 1>{}) : f(Variant<DT, MODE, LPP, 0>{});
+}
+
 template <int DT, int LPP, class F>
 static auto with_mode_rec(int mode, int rec, F&& f) {
-    if (mode == MODE_LINEAR) return rec ? f(Variant<DT, MODE_LINEAR, LPP, 1>{}) : f(Variant<DT, MODE_LINEAR, LPP, 0>{});
-    return rec ? f(Variant<DT, MODE_FROZEN, LPP, 1>{}) : f(Variant<DT, MODE_FROZEN, LPP, 0>{});
+    if constexpr (LPP == 2) {  // two lanes per particle: the FP32 sampler only
+        return (mode & MODE_FROZEN) ? with_rec<DT, LPP, MODE_FROZEN>(rec, f) : with_rec<DT, LPP, MODE_LINEAR>(rec, f);
+    } else {
+        switch (mode) {
+        case MODE_LINEAR: return with_rec<DT, LPP, MODE_LINEAR>(rec, f);
+        case MODE_FROZEN: return with_rec<DT, LPP, MODE_FROZEN>(rec, f);
+        case MODE_LINEAR | MODE_FP64: return with_rec<DT, LPP, MODE_LINEAR | MODE_FP64>(rec, f);
+        default: return with_rec<DT, LPP, MODE_FROZEN | MODE_FP64>(rec, f);
+        }
+    }
 }
 
 template <class F>
 static auto with_variant(int dtype, int mode, int lpp, int rec, F&& f) {
     switch (dtype) {
-    case DT_F32: return lpp == 2 ? with_mode_rec<DT_F32, 2>(mode, rec, f) : with_mode_rec<DT_F32, 1>(mode, rec, f);
+    // two lanes per particle only with the FP32 sampler
+    case DT_F32:
+        return lpp == 2 && !(mode & MODE_FP64) ? with_mode_rec<DT_F32, 2>(mode, rec, f)
+                                               : with_mode_rec<DT_F32, 1>(mode, rec, f);
     case DT_F16: return with_mode_rec<DT_F16, 1>(mode, rec, f);
     default: return with_mode_rec<DT_BF16, 1>(mode, rec, f);
     }

@@ -638,8 +638,9 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
     if (!d_fields || !times) return fail(c, BTO_EINVAL, "null field or time array");
     if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
     if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
-    const int mode = flags & ~(BTO_RECORD_EXIT | BTO_RECORD_CKPT);
-    if (mode != BTO_TIME_LINEAR && mode != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    const int tmode = flags & ~(BTO_RECORD_EXIT | BTO_RECORD_CKPT | BTO_SAMPLE_FP64);
+    if (tmode != BTO_TIME_LINEAR && tmode != BTO_TIME_FROZEN) return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    const int mode = tmode | ((flags & BTO_SAMPLE_FP64) ? MODE_FP64 : 0);
     const int rec = (flags & BTO_RECORD_EXIT) ? 1 : 0;
     const bool rec_ck = (flags & BTO_RECORD_CKPT) != 0;
     for (int32_t q = 0; q <= n_steps; ++q)

@@ -1,11 +1,13 @@
 // Device-side building blocks of the BTO advection path for gfx950.
 //
 // Particle state between launches: the grid cell (10 bits per axis, packed in
-// one dword) plus the FP32 offset inside it -- one 16-byte record, loaded and
-// stored as a single dwordx4.  Inside a launch the position lives in FP64
-// registers (cell + offset is exact in FP64), so stage points and the step
-// update are formed in FP64 and the boundary test is exact; the velocity
-// sampler itself runs in FP32.
+// one dword) plus the offset inside it as three 32-bit fixed-point fractions
+// -- one 16-byte record, loaded and stored as a single dwordx4.  Inside a
+// launch the position lives in FP64 registers (cell + offset is exact in
+// FP64), so stage points and the step update are formed in FP64 and the
+// boundary test is exact; the velocity sampler runs in FP32 (or FP64 on
+// request).  Storing a position between launches rounds it by at most 2^-33
+// cells.
 //
 // Velocity grids stay in the caller's layout (AoS xyz per point, x fastest).
 // The sampler reads each cell as four x-rows of two adjacent points (24 bytes
@@ -35,6 +37,14 @@ constexpr int S_DEFER = 3;
 constexpr int ADJ_DROPPED = 3, ADJ_DROPPED_PARTIAL = 4;
 enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 enum : int { MODE_LINEAR = 0, MODE_FROZEN = 1 };
+// Mode bit: the sampler (in-cell offsets, weights, weighted sums, stage
+// velocities) in FP64 instead of FP32.
+constexpr int MODE_FP64 = 2;
+template <int MODE>
+constexpr bool is_frozen = (MODE & MODE_FROZEN) != 0;
+// Arithmetic type of the sampler in a mode.
+template <int MODE>
+using SampleT = typename std::conditional<(MODE & MODE_FP64) != 0, double, float>::type;
 // Per-seed record of an ended particle: flag << 28 | bits below | exit step.
 constexpr int32_t META_LIVE = -1;          // record slot of a particle still advancing
 constexpr int META_SHIFT = 28;
@@ -44,23 +54,31 @@ constexpr int32_t META_STEP = (1 << 26) - 1;
 
 struct __align__(16) PState {
     uint32_t cell;  // cx | cy << 10 | cz << 20
-    float f[3];     // offset inside the cell, [0, 1]
+    uint32_t q[3];  // offset inside the cell in units of 2^-32 (fixed point, [0, 1))
 };
 
+constexpr double OFFSET_UNIT = 1.0 / 4294967296.0;  // 2^-32
+
+// The position cell + q * 2^-32 is exact in FP64 (10 + 32 bits).
 __device__ __forceinline__ void unpack(const PState& s, double x[3]) {
-    x[0] = (double)(s.cell & 1023u) + (double)s.f[0];
-    x[1] = (double)((s.cell >> 10) & 1023u) + (double)s.f[1];
-    x[2] = (double)((s.cell >> 20) & 1023u) + (double)s.f[2];
+    x[0] = (double)(s.cell & 1023u) + (double)s.q[0] * OFFSET_UNIT;
+    x[1] = (double)((s.cell >> 10) & 1023u) + (double)s.q[1] * OFFSET_UNIT;
+    x[2] = (double)((s.cell >> 20) & 1023u) + (double)s.q[2] * OFFSET_UNIT;
 }
 
+// Nearest representable state (error <= 2^-33 cells per axis): an offset that
+// rounds up to a whole cell moves to the next cell.  x must be inside the
+// block (0 <= x_d <= n_d - 1 <= 1023).
 __device__ __forceinline__ PState pack(const double x[3]) {
     PState s;
     uint32_t c[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double fl = floor(x[d]);
-        c[d] = (uint32_t)(int)fl;
-        s.f[d] = (float)(x[d] - fl);
+        const double r = rint((x[d] - fl) * 4294967296.0);  // exact product, integer in [0, 2^32]
+        const bool carry = r >= 4294967296.0;
+        c[d] = (uint32_t)(int)fl + (carry ? 1u : 0u);
+        s.q[d] = carry ? 0u : (uint32_t)r;
     }
     s.cell = c[0] | (c[1] << 10) | (c[2] << 20);
     return s;
@@ -81,27 +99,33 @@ __device__ __forceinline__ bool inside(const Geom& g, const double p[3]) {
            p[2] >= 0.0 && p[2] <= g.nmax[2];
 }
 
-// Sampling cell i_d = min(floor(p_d), n_d - 2) and FP32 offset f_d = p_d - i_d.
-struct Cell {
+// Sampling cell i_d = min(floor(p_d), n_d - 2) and offset f_d = p_d - i_d,
+// rounded to the sampler's type R (FP32 unless sampling in FP64).
+template <class R>
+struct CellR {
     uint32_t base;  // point index of corner (i, j, k)
     int i[3];       // the cell indices (i, j, k)
-    float f[3];
+    R f[3];
 };
+using Cell = CellR<float>;
 
-__device__ __forceinline__ Cell locate(const Geom& g, const double p[3]) {
-    Cell c;
+template <class R = float>
+__device__ __forceinline__ CellR<R> locate(const Geom& g, const double p[3]) {
+    CellR<R> c;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         int v = (int)floor(p[d]);
         v = v > g.n[d] - 2 ? g.n[d] - 2 : v;
         c.i[d] = v;
-        c.f[d] = (float)(p[d] - (double)v);
+        c.f[d] = (R)(p[d] - (double)v);
     }
     c.base = (uint32_t)c.i[0] + g.sy * (uint32_t)c.i[1] + g.sz * (uint32_t)c.i[2];
     return c;
 }
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return fma(a, b, c); }
 
 // ---------------------------------------------------------------------------
 // Corner values of one cell of one grid level, held in registers across the
@@ -179,11 +203,12 @@ __device__ __forceinline__ void ensure(const Geom& g, const char* V, uint32_t ba
 }
 
 // Trilinear corner weights w[r][x] (row r as above, x-offset x), times `scale`.
-__device__ __forceinline__ void corner_weights(const float f[3], float scale, float w[4][2]) {
-    const float wz0 = (1.f - f[2]) * scale, wz1 = f[2] * scale;
-    const float wy0 = 1.f - f[1], wy1 = f[1];
-    const float yz[4] = {wy0 * wz0, wy1 * wz0, wy0 * wz1, wy1 * wz1};
-    const float wx0 = 1.f - f[0], wx1 = f[0];
+template <class R>
+__device__ __forceinline__ void corner_weights(const R f[3], R scale, R w[4][2]) {
+    const R wz0 = ((R)1 - f[2]) * scale, wz1 = f[2] * scale;
+    const R wy0 = (R)1 - f[1], wy1 = f[1];
+    const R yz[4] = {wy0 * wz0, wy1 * wz0, wy0 * wz1, wy1 * wz1};
+    const R wx0 = (R)1 - f[0], wx1 = f[0];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         w[r][0] = yz[r] * wx0;
@@ -191,18 +216,19 @@ __device__ __forceinline__ void corner_weights(const float f[3], float scale, fl
     }
 }
 
-// Trilinear interpolation of one level.
-template <class CA>
-__device__ __forceinline__ void trilerp(const CA& A, const float f[3], float out[3]) {
-    float w[4][2];
-    corner_weights(f, 1.f, w);
+// Trilinear interpolation of one level, in the arithmetic of R (the corner
+// values are FP32 numbers, exact in either type).
+template <class CA, class R>
+__device__ __forceinline__ void trilerp(const CA& A, const R f[3], R out[3]) {
+    R w[4][2];
+    corner_weights<R>(f, (R)1, w);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float acc = w[0][0] * A.v(0, c);
+        R acc = w[0][0] * (R)A.v(0, c);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (r) acc = fmaf(w[r][0], A.v(r, c), acc);
-            acc = fmaf(w[r][1], A.v(r, 3 + c), acc);
+            if (r) acc = fmar(w[r][0], (R)A.v(r, c), acc);
+            acc = fmar(w[r][1], (R)A.v(r, 3 + c), acc);
         }
         out[c] = acc;
     }
@@ -210,19 +236,19 @@ __device__ __forceinline__ void trilerp(const CA& A, const float f[3], float out
 
 // Trilinear interpolation of the time midpoint (A + B) / 2 of two levels:
 // the factor 1/2 is folded into the weights.
-template <class CA>
-__device__ __forceinline__ void trilerp_mid(const CA& A, const CA& B, const float f[3], float out[3]) {
-    float w[4][2];
-    corner_weights(f, 0.5f, w);
+template <class CA, class R>
+__device__ __forceinline__ void trilerp_mid(const CA& A, const CA& B, const R f[3], R out[3]) {
+    R w[4][2];
+    corner_weights<R>(f, (R)0.5, w);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float acc = w[0][0] * A.v(0, c);
+        R acc = w[0][0] * (R)A.v(0, c);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (r) acc = fmaf(w[r][0], A.v(r, c), acc);
-            acc = fmaf(w[r][0], B.v(r, c), acc);
-            acc = fmaf(w[r][1], A.v(r, 3 + c), acc);
-            acc = fmaf(w[r][1], B.v(r, 3 + c), acc);
+            if (r) acc = fmar(w[r][0], (R)A.v(r, c), acc);
+            acc = fmar(w[r][0], (R)B.v(r, c), acc);
+            acc = fmar(w[r][1], (R)A.v(r, 3 + c), acc);
+            acc = fmar(w[r][1], (R)B.v(r, 3 + c), acc);
         }
         out[c] = acc;
     }
@@ -383,14 +409,14 @@ struct LdsCache {
 
 // Bring a cell's corner values into the cache.  Global caches always succeed;
 // an LDS cache fails when the cell lies outside the staged box.
-template <int DT, class Cache>
-__device__ __forceinline__ bool fetch(const Geom& g, const char* V, const Cell& c, Cache& k) {
+template <int DT, class Cache, class C>
+__device__ __forceinline__ bool fetch(const Geom& g, const char* V, const C& c, Cache& k) {
     ensure<DT>(g, V, c.base, k);
     return true;
 }
 
-template <int DT>
-__device__ __forceinline__ bool fetch(const Geom&, const char*, const Cell& c, LdsCache<DT>& k) {
+template <int DT, class C>
+__device__ __forceinline__ bool fetch(const Geom&, const char*, const C& c, LdsCache<DT>& k) {
     if (k.base == c.base) return true;
     const int lx = c.i[0] - k.lo[0], ly = c.i[1] - k.lo[1], lz = c.i[2] - k.lo[2];
     if ((unsigned)lx > (unsigned)k.lim[0] || (unsigned)ly > (unsigned)k.lim[1] || (unsigned)lz > (unsigned)k.lim[2])
@@ -405,7 +431,8 @@ __device__ __forceinline__ bool fetch(const Geom&, const char*, const Cell& c, L
     return true;
 }
 
-__device__ __forceinline__ bool finite3(const float k[3]) {
+template <class R>
+__device__ __forceinline__ bool finite3(const R k[3]) {
     return __builtin_isfinite(k[0]) && __builtin_isfinite(k[1]) && __builtin_isfinite(k[2]);
 }
 
@@ -465,12 +492,13 @@ __device__ __forceinline__ void exit_face(const Geom& g, const double x[3], cons
 template <int DT, int MODE, class Cache, class OnExit>
 __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const char* V1, double h, double* x,
                                         Cache& LA, Cache& LB, OnExit&& on_exit) {
+    using R = SampleT<MODE>;
     const double hs[3] = {h * g.inv_sp[0], h * g.inv_sp[1], h * g.inv_sp[2]};
-    float k1[3], k2[3], k3[3], k4[3];
+    R k1[3], k2[3], k3[3], k4[3];
     double y[3];
-    Cell c;
+    CellR<R> c;
 
-    c = locate(g, x);
+    c = locate<R>(g, x);
     if (!fetch<DT>(g, V0, c, LA)) return S_DEFER;
     trilerp(LA, c.f, k1);
     if (!finite3(k1)) return S_INVALID;
@@ -481,9 +509,9 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
         return S_TERMINATED;
     }
 
-    c = locate(g, y);
+    c = locate<R>(g, y);
     if (!fetch<DT>(g, V0, c, LA)) return S_DEFER;
-    if (MODE == MODE_LINEAR) {
+    if (!is_frozen<MODE>) {
         if (!fetch<DT>(g, V1, c, LB)) return S_DEFER;
         trilerp_mid(LA, LB, c.f, k2);
     } else {
@@ -497,9 +525,9 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
         return S_TERMINATED;
     }
 
-    c = locate(g, y);
+    c = locate<R>(g, y);
     if (!fetch<DT>(g, V0, c, LA)) return S_DEFER;
-    if (MODE == MODE_LINEAR) {
+    if (!is_frozen<MODE>) {
         if (!fetch<DT>(g, V1, c, LB)) return S_DEFER;
         trilerp_mid(LA, LB, c.f, k3);
     } else {
@@ -513,8 +541,8 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
         return S_TERMINATED;
     }
 
-    c = locate(g, y);
-    if (MODE == MODE_LINEAR) {
+    c = locate<R>(g, y);
+    if (!is_frozen<MODE>) {
         if (!fetch<DT>(g, V1, c, LB)) return S_DEFER;
         trilerp(LB, c.f, k4);
     } else {
@@ -524,7 +552,7 @@ __device__ __forceinline__ int rk4_step(const Geom& g, const char* V0, const cha
     if (!finite3(k4)) return S_INVALID;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const float ks = (k1[d] + k4[d]) + 2.0f * (k2[d] + k3[d]);
+        const R ks = (k1[d] + k4[d]) + (R)2 * (k2[d] + k3[d]);
         y[d] = fma(hs[d] * (1.0 / 6.0), (double)ks, x[d]);
     }
     if (!inside(g, y)) {
@@ -547,12 +575,12 @@ __device__ __forceinline__ int rk4_step_alt(const Geom& g, const char* V0, const
     const auto no_exit = [](const double*) {};
     if ((s & 1) == 0) {
         status = rk4_step<DT, MODE>(g, V0, V1, h, st.x, st.A, st.B, no_exit);
-        if (MODE == MODE_LINEAR) st.A.base = NO_CELL;  // will receive level n+2
+        if (!is_frozen<MODE>) st.A.base = NO_CELL;  // will receive level n+2
     } else {
         status = rk4_step<DT, MODE>(g, V0, V1, h, st.x, st.B, st.A, no_exit);
-        if (MODE == MODE_LINEAR) st.B.base = NO_CELL;
+        if (!is_frozen<MODE>) st.B.base = NO_CELL;
     }
-    if (MODE != MODE_LINEAR) st.A.base = st.B.base = NO_CELL;
+    if (is_frozen<MODE>) st.A.base = st.B.base = NO_CELL;
     return status;
 }
 

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(BLOCK) void seed_explicit_kernel(const SeedExplicit
             // outside the block from the start: terminated at step 0, end = seed
             PState s;
             s.cell = 0;
-            s.f[0] = s.f[1] = s.f[2] = 0.f;
+            s.q[0] = s.q[1] = s.q[2] = 0u;
             a.rec_pos[t] = s;  // position taken from seed_xyz by the writer
             a.rec_meta[t] = (S_TERMINATED << META_SHIFT) | META_OUTSIDE;
         }

@@ -243,7 +243,7 @@ template <int DT, int MODE, int S>
 struct StageRegs {
     static constexpr int NPT = S * S * S;
     static constexpr int KP = (NPT + BLOCK - 1) / BLOCK;
-    static constexpr int NL = MODE == MODE_LINEAR ? 2 : 1;
+    static constexpr int NL = is_frozen<MODE> ? 1 : 2;
     static constexpr int EB = DT == DT_F32 ? 16 : 8;  // LDS bytes per staged point
     static constexpr uint32_t PLANE = (uint32_t)NPT * EB;
     using Pt = typename std::conditional<DT == DT_F32, Pt32, Pt16>::type;
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(BLOCK) void tile_stage_kernel(const TileStepArgs a)
     __syncthreads();
     LdsCache<DT> A, B;
     A.plane = lds;
-    B.plane = lds + (MODE == MODE_LINEAR ? SR::PLANE : 0u);
+    B.plane = lds + (is_frozen<MODE> ? 0u : SR::PLANE);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         A.lo[d] = B.lo[d] = lo[d];
@@ -626,17 +626,16 @@ static hipError_t launch_tile_list_t(const TileListArgs& a, int grid, hipStream_
 
 template <class F>
 static hipError_t tile_dispatch(int dtype, int mode, int rec, F&& f) {
+    auto by_rec = [&](auto dt, auto md) {
+        return rec ? f(dt, md, std::integral_constant<int, 1>{}) : f(dt, md, std::integral_constant<int, 0>{});
+    };
     auto by_mode = [&](auto dt) {
-        constexpr int DT = decltype(dt)::value;
-        if (mode == MODE_LINEAR)
-            return rec ? f(std::integral_constant<int, DT>{}, std::integral_constant<int, MODE_LINEAR>{},
-                           std::integral_constant<int, 1>{})
-                       : f(std::integral_constant<int, DT>{}, std::integral_constant<int, MODE_LINEAR>{},
-                           std::integral_constant<int, 0>{});
-        return rec ? f(std::integral_constant<int, DT>{}, std::integral_constant<int, MODE_FROZEN>{},
-                       std::integral_constant<int, 1>{})
-                   : f(std::integral_constant<int, DT>{}, std::integral_constant<int, MODE_FROZEN>{},
-                       std::integral_constant<int, 0>{});
+        switch (mode) {
+        case MODE_LINEAR: return by_rec(dt, std::integral_constant<int, MODE_LINEAR>{});
+        case MODE_FROZEN: return by_rec(dt, std::integral_constant<int, MODE_FROZEN>{});
+        case MODE_LINEAR | MODE_FP64: return by_rec(dt, std::integral_constant<int, MODE_LINEAR | MODE_FP64>{});
+        default: return by_rec(dt, std::integral_constant<int, MODE_FROZEN | MODE_FP64>{});
+        }
     };
     switch (dtype) {
     case DT_F32: return by_mode(std::integral_constant<int, DT_F32>{});

@@ -139,8 +139,8 @@ def test_streaming_one_call_per_cycle_matches_one_call():
         compare(r, o, label=lab)
         amb = o["margin"] < 1e-6
         assert np.array_equal(r["flag"][~amb], a["flag"][~amb])
-        # each launch re-rounds the in-cell offset to FP32 (<= 2^-25 per launch)
-        assert np.abs(r["end"] - a["end"]).max() < 5e-6
+        # each launch re-rounds the position to the stored state (<= 2^-33 cells per launch)
+        assert np.abs(r["end"] - a["end"]).max() < 1e-7
 
 
 def test_ragged_block_and_lattice_all_dtypes():

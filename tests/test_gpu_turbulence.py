@@ -135,6 +135,42 @@ def test_turb_256_precision_workload_sampled_parity():
         assert res["frac_over_1e-5"] < 0.05
 
 
+def test_turb_256_fp32_grids_sampled_in_fp64_meet_a_flat_1e5():
+    """FP32 grids sampled in FP64 (BTO_SAMPLE_FP64): every sampled seed of the
+    256^3 precision workload that is valid on both sides ends within a flat
+    1e-5 cells of the FP64 oracle on the same stored values (the FP32 sampler
+    needs the Jacobian-stretched bound for 0.4-0.5% of them), with the same
+    flags; in the tile layout too."""
+    import torch
+    from paper_2004_02003_amd import Context
+
+    wl = WORKLOADS["turb_256"]
+    s = wl.make_field()
+    dev = _turb.DeviceTurbulence(s.lazy)
+    ids = np.arange(0, wl.n_seeds, 509)
+    seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
+    o = oracle.flowmap(oracle.Field.lazy_turbulence(s, "f32"), s.times, seeds, wl.n_steps)
+    grids = [dev.fill(c, "f32", _empty(s.n, "f32")) for c in range(wl.n_steps + 1)]
+    for tune in (dict(), dict(tiles=2)):
+        _say(f"{wl.name} f32 sampled in FP64 {tune}")
+        with Context(wl.n, wl.n_seeds) as ctx:
+            ctx.set_tuning(**tune)
+            ctx.seed(wl.stride)
+            if tune:
+                for c in range(wl.n_steps):
+                    ctx.advect(grids[c:c + 2], s.times[c:c + 2], fp64=True)
+            else:
+                ctx.advect(grids, s.times, fp64=True)
+            fm = ctx.flowmap()
+            torch.cuda.synchronize()
+            g = {k: v.cpu().numpy()[ids] for k, v in fm.items() if k != "seed"}
+        res = compare(g, o, pos_tol=1e-5, label=f"{wl.name}/f32/fp64 {tune}")
+        _say(f"max err {res['max_err']:.2e}")
+        assert res["max_err"] < 1e-5
+    del grids
+    torch.cuda.empty_cache()
+
+
 def test_turb_512_scale_workload_ring_and_jacobian_subset():
     import torch
     from paper_2004_02003_amd import Context, jacobian_ftle

@@ -105,6 +105,7 @@ def test_python_binding_mirrors_the_header():
     consts = _header_constants()
     for name in ("BTO_OK", "BTO_EINVAL", "BTO_ENOMEM", "BTO_EHIP", "BTO_ESTATE", "BTO_ERANGE", "BTO_F32",
                  "BTO_F16", "BTO_BF16", "BTO_TIME_LINEAR", "BTO_TIME_FROZEN", "BTO_RECORD_EXIT", "BTO_RECORD_CKPT",
+                 "BTO_SAMPLE_FP64",
                  "BTO_VALID", "BTO_TERMINATED", "BTO_INVALID", "BTO_ADJ_DROPPED", "BTO_ADJ_DROPPED_PARTIAL"):
         assert getattr(_lib, name) == consts[name], name
     ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double}
