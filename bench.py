@@ -258,15 +258,15 @@ def precision_statement(log, threads):
     """End-position error of the GPU path against the FP64 oracle on the FP64
     field, per storage type, for the turbulence blocks: the 256^3 precision
     workload in f32/f16/bf16 on every 509th seed (4,121 seeds), and the 512^3
-    scale workload in f16 on every 256th seed (65,536 seeds), both through a
-    two-slot ring with one call per cycle.  Mean, p99 and max over the seeds
+    scale workload in f16 on 65,536 seeds (one per lattice row, spread over
+    x), both through a two-slot ring with one call per cycle.  Mean, p99 and max over the seeds
     valid on both sides, the share beyond 1e-5 cells, and the first-order bound
     ||J|| N h max|V| sqrt(3) (u_storage + 2^-21) per seed (J from the oracle's
     FP64 tangent, u the storage's unit roundoff, 2^-21 the FP32 sampling)."""
     import torch
     import oracle
     from bto_inputs import _turb
-    from bto_inputs.workloads import WORKLOADS
+    from bto_inputs.workloads import WORKLOADS, lattice_dims, row_sample_ids
     from paper_2004_02003_amd import Context
 
     out = {}
@@ -275,7 +275,10 @@ def precision_statement(log, threads):
         s = wl.make_field()
         gen = _turb.DeviceTurbulence(s.lazy)
         N = wl.n_steps
-        ids = np.arange(0, wl.n_seeds, every)
+        if every == 256:  # one seed per lattice row, its x index cycling (a plain stride of 256 keeps x fixed)
+            ids = row_sample_ids(lattice_dims(wl.n, wl.stride), wl.n_seeds // every)
+        else:
+            ids = np.arange(0, wl.n_seeds, every)
         seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
         t0 = time.perf_counter()
         o = oracle.flowmap(oracle.Field.lazy_turbulence(s, "f64"), s.times, seeds, N, jac=True, nthreads=threads)
@@ -315,7 +318,8 @@ def precision_statement(log, threads):
                        "flag_disagree": int((flag != o["flag"]).sum()),
                        "flag_disagree_outside_margin": int(((flag != o["flag"]) & safe).sum())}
             log(f"precision {name} {key}: {res[key]}")
-        out[name] = {"seeds": f"every {every}th of {wl.n_seeds} ({len(ids)})", "steps": N,
+        pick = "one per lattice row, x index cycling" if every == 256 else f"every {every}th"
+        out[name] = {"seeds": f"{pick} of {wl.n_seeds} ({len(ids)})", "steps": N,
                      "cells": "end-position L2 error, cells", **res}
     return out
 
@@ -760,8 +764,10 @@ def cpu_baseline_of(wl, series, dt, turb, grids_host, log, target_s=10.0):
     import oracle
 
     P = wl.n_seeds
+    from bto_inputs.workloads import lattice_dims, row_sample_ids
+
     every = 1 if not turb else (4096 if wl.n[0] >= 512 else 1024)
-    ids = np.arange(0, P, every)
+    ids = row_sample_ids(lattice_dims(wl.n, wl.stride), P // every) if every > 1 else np.arange(P)
     seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
     N = wl.n_steps
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
@@ -786,7 +792,7 @@ def cpu_baseline_of(wl, series, dt, turb, grids_host, log, target_s=10.0):
                   if turb else "dense grids")
     res = {"value": round(ps / tc, 1), "unit": "particle-RK4-steps/s", "cores": threads, "kind": "oracle",
            "cpu": cpu_model, "nproc": os.cpu_count(),
-           "sample": f"{'all' if every == 1 else f'every {every}th'} seed(s) of {wl.name} ({len(ids)} seeds x {N} "
+           "sample": f"{'all' if every == 1 else f'one in {every} ({len(ids)}, spread over the lattice rows)'} seed(s) of {wl.name} ({len(ids)} seeds x {N} "
                      f"steps, {dt} storage, {field_note}) x {reps} repeats, {ps} particle-steps in {tc:.1f} s, "
                      f"FP64, OpenMP"}
     ids1 = ids[::16]

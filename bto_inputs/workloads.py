@@ -81,3 +81,22 @@ def loss_weights(n_seeds: int, seed: int = 3) -> np.ndarray:
     """Seeded N(0, I_3) weights for the scalar loss sum_i w_i . x_i(T)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal((n_seeds, 3))
+
+
+def lattice_dims(n, stride: int):
+    """Seeds per axis of the lattice off + stride*k (off = (stride-1)/2) that
+    stays inside [0, n-1] on each axis."""
+    off = (stride - 1) / 2.0
+    return tuple(int((int(nd) - 1 - off) // stride) + 1 for nd in n)
+
+
+def row_sample_ids(m, count: int) -> np.ndarray:
+    """Ids of ``count`` seeds of an x-fastest lattice of m = (mx, my, mz)
+    seeds, spread over the block: the chosen rows (y, z) are every
+    (my*mz // count)-th row, and the i-th chosen row gives its seed at x
+    index i mod mx, so every x index appears as often as the others (plain
+    strides of the id would keep x fixed whenever they divide mx)."""
+    mx, rows = int(m[0]), int(m[1]) * int(m[2])
+    every = max(1, rows // count)
+    r = np.arange(0, rows, every, dtype=np.int64)[:count]
+    return r * mx + (np.arange(len(r), dtype=np.int64) % mx)

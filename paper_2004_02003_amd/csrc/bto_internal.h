@@ -192,6 +192,7 @@ constexpr int TILE_S_F32 = 13;  // FP32 grids (tile of 8 cells)
 // storage type (216 particles at stride 2; long 48 x 6 x 6 tiles, whose
 // wavefronts share longer grid rows, measured the same).
 constexpr int TILE_GATHER[3] = {12, 12, 12};
+constexpr int GATHER_NT = 256;  // threads per workgroup of the gathering tile step
 
 __host__ __device__ constexpr int tile_side(int dtype, int staged, int axis) {
     return staged ? (dtype == DT_F32 ? TILE_S_F32 : TILE_S_16) - 1 - 2 * TILE_H : TILE_GATHER[axis];

@@ -113,10 +113,11 @@ __device__ __forceinline__ void append_list(bool on, const PState& st, uint32_t 
     }
 }
 
-// Workgroup totals of particle-steps and survivors into the XCD's counters.
+// Workgroup totals of particle-steps and survivors into the XCD's counters
+// (NT threads per workgroup).
+template <int NT>
 __device__ __forceinline__ void add_totals(uint32_t steps, uint32_t surv, unsigned long long* psteps,
-                                           uint32_t* live, uint32_t* s_red) {
-    constexpr int W = BLOCK / WAVE;
+                                           uint32_t* live, uint32_t* s_red, int W = NT / WAVE) {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1) {
@@ -126,16 +127,15 @@ __device__ __forceinline__ void add_totals(uint32_t steps, uint32_t surv, unsign
     __syncthreads();
     if (lane == 0) {
         s_red[wave] = steps;
-        s_red[W + wave] = surv;
+        s_red[NT / WAVE + wave] = surv;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long ts = 0;
         uint32_t tl = 0;
-#pragma unroll
         for (int w = 0; w < W; ++w) {
             ts += s_red[w];
-            tl += s_red[W + w];
+            tl += s_red[NT / WAVE + w];
         }
         const int xcd = blockIdx.x % NSEG;
         if (ts) atomicAdd(&psteps[xcd], ts);
@@ -321,14 +321,16 @@ __device__ __forceinline__ void tile_batch(const TileStepArgs& a, bool alive, co
 // rows: each row load of the sampler then touches a few cache lines per
 // wavefront instead of one per lane.  Block-uniform.
 constexpr int SORT_ROWS_MAX = 16 * 16;  // rows of the largest tile (y, z sides <= 16)
+template <int NT>
 struct SortLds {
     uint32_t off[SORT_ROWS_MAX + 64];
-    PState pos[BLOCK];
-    uint32_t id[BLOCK];
+    PState pos[NT];
+    uint32_t id[NT];
 };
 
+template <int NT>
 __device__ __forceinline__ void sort_rows(const TileGeom& tg, const int tc[3], bool on, PState& st, uint32_t& id,
-                                          SortLds& s) {
+                                          SortLds<NT>& s, int nthr = NT) {
     const int Ty = tg.T[1], Tz = tg.T[2];
     const int nrow = Ty * Tz;  // bin nrow: lanes without a particle, last
     uint32_t key = (uint32_t)nrow;
@@ -339,7 +341,7 @@ __device__ __forceinline__ void sort_rows(const TileGeom& tg, const int tc[3], b
         lz = lz < 0 ? 0 : (lz > Tz - 1 ? Tz - 1 : lz);
         key = (uint32_t)(lz * Ty + ly);
     }
-    for (int i = threadIdx.x; i <= nrow; i += BLOCK) s.off[i] = 0u;
+    for (int i = threadIdx.x; i <= nrow; i += nthr) s.off[i] = 0u;
     __syncthreads();
     const uint32_t rank = atomicAdd(&s.off[key], 1u);
     __syncthreads();
@@ -377,15 +379,15 @@ __device__ __forceinline__ void sort_rows(const TileGeom& tg, const int tc[3], b
 }
 
 // ---------------------------------------------------------------------------
-// Gathering tile step: one workgroup per tile, the particles gather from the
-// grids (through L2, which the tile order keeps warm).
+// Gathering tile step: one workgroup of NT threads per tile, the particles
+// gather from the grids (through L2, which the tile order keeps warm).
 // ---------------------------------------------------------------------------
-template <int DT, int MODE, int REC>
-__global__ __launch_bounds__(BLOCK) void tile_gather_kernel(const TileStepArgs a) {
-    __shared__ uint32_t s_red[2 * (BLOCK / WAVE)];
+template <int DT, int MODE, int REC, int NT>
+__global__ __launch_bounds__(NT) void tile_gather_kernel(const TileStepArgs a) {
+    __shared__ uint32_t s_red[2 * (NT / WAVE)];
     __shared__ uint32_t s_hist[32], s_base[32];
     __shared__ int32_t s_nb[32];
-    __shared__ SortLds s_sort;
+    __shared__ SortLds<NT> s_sort;
     if (blockIdx.x == 0 && threadIdx.x < NSEG) a.live_clear[threadIdx.x] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == NSEG) *a.list_clear = 0u;
     // bucket b = this workgroup: its tile, count and first particles load at once
@@ -403,14 +405,23 @@ __global__ __launch_bounds__(BLOCK) void tile_gather_kernel(const TileStepArgs a
     if (threadIdx.x == 0) a.tc_clear[b] = 0u;
     cnt = cnt < a.out.cap ? cnt : a.out.cap;
     if (cnt == 0) return;
+    // A tile with fewer particles than threads: the wavefronts past its count
+    // end here, so they hold no wave slot while the tile runs (s_barrier then
+    // waits for the surviving wavefronts only).  The wave index is taken from
+    // the first lane so that the branch is scalar: the whole wavefront ends.
+    int nw = NT / WAVE;
+    if (cnt < (uint32_t)NT) {
+        nw = (int)((cnt + WAVE - 1) / WAVE);
+        if (__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)) >= nw) return;
+    }
     int tc[3], lo[3], ext[3];
     tile_box(a.g, a.tg, t, tc, lo, ext);
     neighbour_buckets(a.tg, a.out, tc, s_nb);
-    if (cnt <= BLOCK) sort_rows(a.tg, tc, threadIdx.x < cnt, st0, id0, s_sort);
+    if (cnt <= NT) sort_rows<NT>(a.tg, tc, threadIdx.x < cnt, st0, id0, s_sort, nw * WAVE);
     const char* V0 = in_global(a.f0);
     const char* V1 = in_global(a.f1);
     uint32_t my_steps = 0, my_surv = 0;
-    for (uint32_t bb = 0; bb < cnt; bb += BLOCK) {
+    for (uint32_t bb = 0; bb < cnt; bb += NT) {
         const uint32_t i = bb + threadIdx.x;
         const bool alive = i < cnt;
         PState st = st0;
@@ -422,7 +433,7 @@ __global__ __launch_bounds__(BLOCK) void tile_gather_kernel(const TileStepArgs a
         CellCache<DT> A, B;
         tile_batch<DT, MODE, REC>(a, alive, st, id, tc, V0, V1, A, B, my_steps, my_surv, s_hist, s_base, s_nb);
     }
-    add_totals(my_steps, my_surv, a.psteps, a.live_out, s_red);
+    add_totals<NT>(my_steps, my_surv, a.psteps, a.live_out, s_red, nw);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,7 +496,7 @@ __global__ __launch_bounds__(BLOCK) void tile_stage_kernel(const TileStepArgs a)
         tile_batch<DT, MODE, REC>(a, alive, st, id, tc, nullptr, nullptr, A, B, my_steps, my_surv, s_hist, s_base,
                                   s_nb);
     }
-    add_totals(my_steps, my_surv, a.psteps, a.live_out, s_red);
+    add_totals<BLOCK>(my_steps, my_surv, a.psteps, a.live_out, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void tile_list_kernel(const TileListArgs a) 
         const uint32_t key = surv ? tile_key(a.s.g, a.s.tg, x) : 0u;
         scatter_survivors(surv, key, pack(x), id, a.s.out);
     }
-    add_totals(my_steps, my_surv, a.s.psteps, a.s.live_out, s_red);
+    add_totals<BLOCK>(my_steps, my_surv, a.s.psteps, a.s.live_out, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -606,7 +617,7 @@ static hipError_t launch_tile_step_t(const TileStepArgs& a, int stage, hipStream
     using SR = StageRegs<DT, MODE, S>;
     constexpr size_t lds = (size_t)SR::NL * SR::PLANE;
     if (!stage) {
-        hipLaunchKernelGGL((tile_gather_kernel<DT, MODE, REC>), dim3(a.order_len), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((tile_gather_kernel<DT, MODE, REC, GATHER_NT>), dim3(a.order_len), dim3(GATHER_NT), 0, s, a);
         return hipGetLastError();
     }
     // LDS beyond the default limit: raise the kernel's dynamic-LDS limit (on

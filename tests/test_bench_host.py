@@ -67,3 +67,23 @@ def test_more_than_one_gpu_is_refused(bench):
     with pytest.raises(SystemExit) as e:
         bench.main(["--gpus", "2"])
     assert e.value.code == 2
+
+
+def test_seed_subsets_spread_over_the_lattice():
+    import numpy as np
+
+    import oracle
+    from bto_inputs.workloads import lattice_dims, row_sample_ids
+
+    for n, stride in (((37, 23, 19), 3), ((40, 30, 20), 2), ((16, 16, 16), 4)):
+        m = lattice_dims(n, stride)
+        assert int(np.prod(m)) == len(oracle.seed_lattice(n, stride))
+    m = (256, 256, 256)
+    ids = row_sample_ids(m, 65536)
+    assert len(ids) == 65536 and len(np.unique(ids)) == 65536 and ids.max() < 256 ** 3
+    x, row = ids % 256, ids // 256
+    assert np.array_equal(np.bincount(x), np.full(256, 256))        # every x index equally often
+    assert np.array_equal(row, np.arange(65536))                     # one seed per row
+    ids = row_sample_ids(m, 4096)
+    assert len(ids) == 4096 and np.array_equal(np.bincount(ids % 256), np.full(256, 16))
+    assert np.all(np.diff(ids // 256) == 16)

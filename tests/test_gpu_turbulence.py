@@ -17,7 +17,7 @@ import pytest
 import oracle
 from bto_inputs import fields
 from bto_inputs import _turb
-from bto_inputs.workloads import WORKLOADS
+from bto_inputs.workloads import WORKLOADS, lattice_dims, row_sample_ids
 
 from .parity import compare
 
@@ -92,6 +92,17 @@ def _run_series(ctx, dev, s, N, dtype, ring=False):
         ctx.advect([slots[c % 2], slots[(c + 1) % 2]], s.times[c:c + 2])
     torch.cuda.synchronize()
     return None
+
+
+def _bench():
+    import importlib.util
+    import os
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(root, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
 
 
 def _jac_tol(o, N, h, vmax):
@@ -179,22 +190,37 @@ def test_turb_512_scale_workload_ring_and_jacobian_subset():
     s = wl.make_field()
     dev = _turb.DeviceTurbulence(s.lazy)
     dt = "f16"
-    _say(f"{wl.name} forward, two-slot ring, {wl.n_seeds} seeds")
-    ids = np.arange(0, wl.n_seeds, 4099)
+    # the forward in the launch configuration the benchmark times (tile layout,
+    # one call per cycle through the two-slot ring), and in the segment layout
+    # at one step per call: the two layouts share the step arithmetic, so the
+    # flow maps of all 16.7M seeds must be identical; a 65,536-seed subset
+    # (one seed per lattice row, its x index cycling) is compared with the
+    # FP64 oracle
+    bench = _bench()
     seeds_all = oracle.seed_lattice(wl.n, wl.stride)
-    with Context(wl.n, wl.n_seeds) as ctx:
-        ctx.set_tuning(rebin_every=10)  # re-sort every 10 steps (results must not change)
-        ctx.seed(wl.stride)
-        _run_series(ctx, dev, s, wl.n_steps, dt, ring=True)
-        fm = ctx.flowmap(count_valid=True)
-        st = ctx.stats()
-        torch.cuda.synchronize()
-        g = {k: v.cpu().numpy()[ids] for k, v in fm.items() if k not in ("n_valid", "seed")}
+    ids = row_sample_ids(lattice_dims(wl.n, wl.stride), 65536)
+    out = {}
+    for label, tune in (("bench shape", bench.insitu_shape(wl.name, dt)), ("segments", dict(tiles=0))):
+        _say(f"{wl.name} forward ({label}: {tune}), two-slot ring, {wl.n_seeds} seeds")
+        with Context(wl.n, wl.n_seeds) as ctx:
+            ctx.set_tuning(**tune)
+            ctx.seed(wl.stride)
+            _run_series(ctx, dev, s, wl.n_steps, dt, ring=True)
+            fm = ctx.flowmap(count_valid=True)
+            st = ctx.stats()
+            torch.cuda.synchronize()
+            out[label] = ({k: v.cpu().numpy() for k, v in fm.items() if k not in ("n_valid", "seed")}, st)
+    (a, st), (b, st_b) = out["bench shape"], out["segments"]
+    for key in a:
+        assert np.array_equal(a[key], b[key]), f"{wl.name}: {key} differs between the tile and segment layouts"
+    assert st["particle_steps"] == st_b["particle_steps"] and st["n_live"] == st_b["n_live"]
+    g = {k: v[ids] for k, v in a.items()}
     o = oracle.flowmap(oracle.Field.lazy_turbulence(s, dt), s.times, seeds_all[ids], wl.n_steps, jac=True)
     vmax = 1.5 / wl.dt * 6.0
     res = compare(g, o, per_particle_tol=_jac_tol(o, wl.n_steps, wl.dt, vmax), label=wl.name)
     _say(f"{wl.name}: {res}; live {st['n_live']} of {st['n_seeds']}, particle-steps {st['particle_steps']}")
     assert 0.35 < 1 - st["n_live"] / st["n_seeds"] < 0.65
+    assert res["n"] == 65536
 
     # Jacobian adjoint on every 16th seed id within the scale workload's memory:
     # the forward runs through the two-slot ring recording checkpoints every 10
