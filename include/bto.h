@@ -315,6 +315,33 @@ int bto_adjoint_segment(bto_ctx *ctx, int32_t segment, const void *const *d_fiel
  * sigma = ln sqrt(lambda_max(J^T J)) / |T| (d_jac: n x 9 floats, d_out: n floats). */
 int bto_ftle(bto_ctx *ctx, const float *d_jac, int64_t n, double T, float *d_out, void *stream);
 
+/* Grid points touched per step by the context's seeds: the count behind the
+ * per-unit byte figure of the advection's roofline (its input-side bytes per
+ * step are the points of level n and of level n + 1 that the step's stage
+ * points sample, times the bytes per point).  At the stride-2 lattice density
+ * this is about 8 points per live particle per level; sparser seedings share
+ * fewer corners and are counted here exactly.  A diagnostic that is not part of
+ * the paper's method: the RK4 step and the trilinear sampler are those of
+ * Section 3.1's advection worklet, and the count is the
+ * bookkeeping of its reads.
+ *   d_fields / times  n_steps + 1 grids (device) and times (host), as for
+ *                     bto_advect_interval; dtype, flags likewise
+ *                     (BTO_TIME_LINEAR / BTO_TIME_FROZEN, optionally
+ *                     | BTO_SAMPLE_FP64);
+ *   d_counts          3 x n_steps unsigned 64-bit counters, device, written:
+ *                     per step n, the distinct points of level n sampled, the
+ *                     distinct points of level n + 1 sampled, and the particles
+ *                     entering the step.
+ * The seeds walk the interval from their seeded positions with the adjoint's
+ * forward (FP64 positions kept between steps), one step per launch, each
+ * sampled cell marking its eight corners in a bitmap of the block's points
+ * per level.  The context's own advection state is not touched.  Allocates
+ * n_seeds x 25 bytes plus two bitmaps (one bit per grid point) for the call
+ * and synchronizes the stream before it returns.  BTO_ESTATE before seeding;
+ * BTO_EINVAL for null pointers, non-increasing times or unknown flags. */
+int bto_touched_points(bto_ctx *ctx, const void *const *d_fields, const double *times, int32_t n_steps,
+                       int32_t dtype, int32_t flags, unsigned long long *d_counts, void *stream);
+
 /* ---- Post hoc side of the seed-lattice flow map (no context needed) ---- */
 
 /* Place one block's seed-ordered flow map (lattice mb[3] points per axis, x

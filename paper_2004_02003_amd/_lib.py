@@ -27,7 +27,7 @@ EXPORTED = [
     "bto_create", "bto_destroy", "bto_last_error", "bto_seed", "bto_seed_explicit",
     "bto_advect_interval", "bto_flowmap_out", "bto_stats", "bto_adjoint_interval", "bto_ftle",
     "bto_set_tuning", "bto_get_tuning", "bto_exit_points", "bto_place_block", "bto_reconstruct_lattice",
-    "bto_flowmap_error", "bto_flowmap_error_static", "bto_adjoint_segment",
+    "bto_flowmap_error", "bto_flowmap_error_static", "bto_adjoint_segment", "bto_touched_points",
 ]
 
 _ERRNAMES = {BTO_EINVAL: "BTO_EINVAL", BTO_ENOMEM: "BTO_ENOMEM", BTO_EHIP: "BTO_EHIP",
@@ -89,6 +89,7 @@ def load() -> ctypes.CDLL:
     L.bto_adjoint_interval.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
     L.bto_adjoint_segment.argtypes = [vp, i32, vp, vp, i32, i32, vp, i32, vp, vp, vp, vp]
     L.bto_ftle.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]
+    L.bto_touched_points.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp]
     L.bto_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.bto_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     for fn in EXPORTED:

@@ -264,6 +264,26 @@ class Context:
             grad_seed.data_ptr() if grad_seed is not None else None, gptr,
             status.data_ptr() if status is not None else None, _stream_ptr(stream)))
 
+    def touched_points(self, grids: Sequence[torch.Tensor], times, mode: str = "linear", fp64: bool = False,
+                       stream=None) -> np.ndarray:
+        """Distinct grid points each step of the interval samples, per level,
+        for the seeds of the last seeding: (N, 3) uint64 rows of (points of
+        level n, points of level n + 1, particles entering step n)."""
+        dt = grids[0].dtype
+        shape = (self.n[2], self.n[1], self.n[0], 3)
+        for g in grids:
+            if g.dtype != dt or tuple(g.shape) != shape or not g.is_contiguous():
+                raise ValueError("grids must share dtype and shape")
+        times = np.ascontiguousarray(np.asarray(times, dtype=np.float64))
+        N = len(grids) - 1
+        if len(times) != N + 1:
+            raise ValueError("one time per grid")
+        ptrs = (ctypes.c_void_p * len(grids))(*[g.data_ptr() for g in grids])
+        out = torch.empty(3 * N, dtype=torch.int64, device=grids[0].device)
+        self._check(self.L.bto_touched_points(self._h, ptrs, times.ctypes.data, N, _TORCH_DT[dt],
+                                              _flags(mode, fp64=fp64), out.data_ptr(), _stream_ptr(stream)))
+        return out.cpu().numpy().astype(np.uint64).reshape(N, 3)
+
     def ftle(self, jac: torch.Tensor, T: float, stream=None) -> torch.Tensor:
         """FTLE per seed from (P, 3, 3) float32 Jacobians."""
         jac = jac.contiguous()

@@ -1181,6 +1181,64 @@ int bto_ftle(bto_ctx* c, const float* d_jac, int64_t n, double T, float* d_out, 
     return BTO_OK;
 }
 
+int bto_touched_points(bto_ctx* c, const void* const* d_fields, const double* times, int32_t n_steps,
+                       int32_t dtype, int32_t flags, unsigned long long* d_counts, void* stream) {
+    int rc = begin(c);
+    if (rc) return rc;
+    if (!d_fields || !times || !d_counts) return fail(c, BTO_EINVAL, "null argument");
+    if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
+    if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
+    const int base_mode = flags & ~BTO_SAMPLE_FP64;
+    if (base_mode != BTO_TIME_LINEAR && base_mode != BTO_TIME_FROZEN)
+        return fail(c, BTO_EINVAL, "unknown flags %d", flags);
+    const int mode = (base_mode == BTO_TIME_FROZEN ? MODE_FROZEN : MODE_LINEAR) |
+                     ((flags & BTO_SAMPLE_FP64) ? MODE_FP64 : 0);
+    for (int32_t q = 0; q <= n_steps; ++q)
+        if (!d_fields[q]) return fail(c, BTO_EINVAL, "field pointer %d is null", q);
+    for (int32_t q = 0; q < n_steps; ++q)
+        if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
+            return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
+    if (!c->seeded) return fail(c, BTO_ESTATE, "touched points counted before seeding");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_touch_zero(d_counts, (size_t)n_steps * 3, s);
+    if (e != hipSuccess) return hip_fail(c, e, "touched points: clear counters");
+    const int64_t P = c->n_seeds;
+    if (P == 0) return BTO_OK;
+    const size_t npts = (size_t)c->geom.n[0] * (size_t)c->geom.n[1] * (size_t)c->geom.n[2];
+    const size_t words = (npts + 31) / 32;
+    const size_t xb = ((size_t)P * 3 * sizeof(double) + 255) & ~(size_t)255;
+    const size_t ab = ((size_t)P + 255) & ~(size_t)255;
+    const size_t bb = ((words * sizeof(uint32_t)) + 255) & ~(size_t)255;
+    char* buf = nullptr;
+    e = hipMalloc(&buf, xb + ab + 2 * bb);
+    if (e != hipSuccess) return hip_fail(c, e, "touched points: scratch allocation");
+    TouchArgs a{};
+    a.g = c->geom;
+    a.P = P;
+    a.seed_xyz = c->seed_xyz;
+    for (int d = 0; d < 3; ++d) a.origin[d] = c->blk.origin[d];
+    a.x = reinterpret_cast<double*>(buf);
+    a.alive = reinterpret_cast<uint8_t*>(buf + xb);
+    a.bits0 = reinterpret_cast<uint32_t*>(buf + xb + ab);
+    a.bits1 = reinterpret_cast<uint32_t*>(buf + xb + ab + bb);
+    e = launch_tile_fill(a.bits0, 2 * bb / sizeof(uint32_t), s);
+    if (e == hipSuccess) e = launch_touch_init(a, s);
+    for (int32_t n = 0; n < n_steps && e == hipSuccess; ++n) {
+        a.f0 = static_cast<const char*>(d_fields[n]);
+        a.f1 = static_cast<const char*>(d_fields[n + 1]);
+        a.h = times[n + 1] - times[n];
+        a.out = d_counts + 3 * (size_t)n;
+        e = launch_touch_step(a, dtype, mode, s);
+        if (e == hipSuccess) e = launch_touch_count(a.bits0, words, a.out, s);
+        if (e == hipSuccess) e = launch_touch_count(a.bits1, words, a.out + 1, s);
+    }
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return hip_fail(c, e, "touched points launch");
+    if (e2 != hipSuccess) return hip_fail(c, e2, "touched points");
+    return BTO_OK;
+}
+
 int bto_set_tuning(bto_ctx* c, const bto_tuning* t) {
     if (!c) return BTO_EINVAL;
     if (!t) return fail(c, BTO_EINVAL, "null tuning");

@@ -308,6 +308,27 @@ hipError_t launch_place(const int32_t mb[3], const int32_t M[3], const int32_t o
                         hipStream_t s);
 hipError_t launch_flowmap(const FlowmapArgs& a, int blocks_per_seg, hipStream_t s);
 hipError_t launch_ckpt_store(const CkptArgs& a, int blocks_per_seg, hipStream_t s);
+
+// Touched grid points per step (diagnostic walk of the seeds, one step per
+// launch).
+struct TouchArgs {
+    Geom g;
+    const char* f0;                 // grids of the step's two cycles
+    const char* f1;
+    double h;                       // step size
+    int64_t P;                      // seeds
+    const double* seed_xyz;         // P x 3 world
+    double origin[3];
+    double* x;                      // P x 3 positions, cell units
+    uint8_t* alive;                 // P
+    uint32_t* bits0;                // bitmaps of the block's points: level n,
+    uint32_t* bits1;                //   level n + 1
+    unsigned long long* out;        // the step's counters: points of level n, n + 1, particles entering
+};
+hipError_t launch_touch_init(const TouchArgs& a, hipStream_t s);
+hipError_t launch_touch_step(const TouchArgs& a, int dtype, int mode, hipStream_t s);
+hipError_t launch_touch_count(uint32_t* bits, size_t words, unsigned long long* out, hipStream_t s);
+hipError_t launch_touch_zero(unsigned long long* p, size_t n, hipStream_t s);
 int advect_max_blocks_per_cu(int dtype, int mode, int lanes_per_particle, int record_exit);
 hipError_t launch_adjoint(const AdjointArgs& a, int dtype, int mode, hipStream_t s);
 size_t grad_sort_temp_bytes(uint64_t n, int bits);

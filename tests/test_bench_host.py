@@ -87,3 +87,19 @@ def test_seed_subsets_spread_over_the_lattice():
     ids = row_sample_ids(m, 4096)
     assert len(ids) == 4096 and np.array_equal(np.bincount(ids % 256), np.full(256, 16))
     assert np.all(np.diff(ids // 256) == 16)
+
+
+def test_adjoint_byte_model_from_touched_points(bench):
+    import numpy as np
+
+    # two steps: 100 + 120 points of level n, 110 + 90 of level n + 1, 10 and 8 particles
+    t = np.array([[100, 110, 10], [120, 90, 8]], dtype=np.uint64)
+    pts, live = 420, 18
+    assert bench.adjoint_alg_bytes(t, "seed_gradient", 2, n_seeds=10) == int(
+        3 * pts * 12 + 48 * live + 48 * live / 2 + 24 * 10)
+    assert bench.adjoint_alg_bytes(t, "seed_and_grid_gradient", 2, n_seeds=10) == int(
+        3 * pts * 12 + 2 * pts * 12 + 48 * live + 48 * live / 2 + 24 * 10)
+    assert bench.adjoint_alg_bytes(t, "seed_gradient_checkpoint_every_step", 2, n_seeds=10) == int(
+        2 * pts * 12 + 48 * live + 24 * 10)
+    assert bench.adjoint_alg_bytes(t, "jacobian_ftle", 2, n_seeds=10, n_cot=3) == int(
+        3 * pts * 12 + 48 * live + 48 * live / 2 + 24 * 30)
