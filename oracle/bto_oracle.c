@@ -390,12 +390,16 @@ static void advect_one(const orc_problem *P, const double x0[3], int want_phi, o
     memcpy(T->phi, phi, sizeof phi);
 }
 
-static void set_threads(int32_t nthreads)
+/* Threads of one call: nthreads if positive, else the OpenMP default.  Passed
+ * to the call's own parallel region (num_threads), so no call changes the
+ * thread count of later calls. */
+static int call_threads(int32_t nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return nthreads > 0 ? (int)nthreads : omp_get_max_threads();
 #else
     (void)nthreads;
+    return 1;
 #endif
 }
 
@@ -410,8 +414,9 @@ int orc_flowmap(const orc_problem *P, int64_t np, const double *seeds, double *e
         if (P->n[d] < 2) return -1;
     for (int32_t s = 0; s < P->n_steps; ++s)
         if (!(P->times[s + 1] > P->times[s])) return -1;
-    set_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 64)
+    const int nt = call_threads(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
     for (int64_t p = 0; p < np; ++p) {
         orc_track T;
         T.stages = NULL;
@@ -462,8 +467,9 @@ int orc_adjoint(const orc_problem *P, int64_t np, const double *seeds, const dou
 {
     if (!P || !P->times || !P->fetch || P->n_steps < 0) return -1;
     const int32_t N = P->n_steps;
-    set_threads(grad_grid ? 1 : nthreads);
-#pragma omp parallel
+    const int nt = grad_grid ? 1 : call_threads(nthreads);
+    (void)nt;
+#pragma omp parallel num_threads(nt)
     {
         double *stages = (double *)malloc(sizeof(double) * 12 * (size_t)(N > 0 ? N : 1));
 #pragma omp for schedule(dynamic, 16)

@@ -137,7 +137,6 @@ __device__ __forceinline__ double fmar(double a, double b, double c) { return fm
 constexpr uint32_t NO_CELL = 0xFFFFFFFFu;
 
 struct __attribute__((packed, aligned(4))) Row32 { float v[6]; };
-struct __attribute__((packed, aligned(2))) Row16 { uint32_t w[3]; };
 
 // Value (r, q) of a row of two 16-bit points packed as three dwords
 // (x0|y0, z0|x1, y1|z1), converted to FP32 (exact).
@@ -151,12 +150,29 @@ __device__ __forceinline__ float dec16(uint32_t w, int hi) {
     }
 }
 
+// A row of two 16-bit points (12 bytes at a 2-byte-aligned offset: half of
+// the rows start off a dword boundary) as three dwords, through one 4-aligned
+// 16-byte load that holds it, shifted into place in registers.  The window
+// starts at most at lim (the grid's size in bytes minus 16), so it never
+// reads beyond the grid.  Misaligned 12-byte loads cost the texture path
+// more than the aligned 16 bytes (6% on the 512^3 f16 in situ step).
+__device__ __forceinline__ void load_row16(const char* V, uint32_t pt, uint64_t lim, uint32_t w[3]) {
+    const uint64_t off = (uint64_t)pt * 6u;
+    uint64_t st = off & ~3ull;
+    st = st < lim ? st : lim;
+    const uint4 q = *reinterpret_cast<const uint4*>(V + st);
+    const uint32_t sh = (uint32_t)(off - st) * 8u;  // 0, 16 or (clamped at the end) 32
+    w[0] = (uint32_t)((((uint64_t)q.y << 32) | q.x) >> sh);
+    w[1] = (uint32_t)((((uint64_t)q.z << 32) | q.y) >> sh);
+    w[2] = (uint32_t)((((uint64_t)q.w << 32) | q.z) >> sh);
+}
+
 template <int DT>
 struct CellCache {
     uint32_t base;
     float R[4][6];
     __device__ __forceinline__ float v(int r, int q) const { return R[r][q]; }
-    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r, uint64_t) {
         const Row32 x = *reinterpret_cast<const Row32*>(V + (uint64_t)pt * 12u);
 #pragma unroll
         for (int q = 0; q < 6; ++q) R[r][q] = x.v[q];
@@ -170,11 +186,8 @@ struct CellCache<DT_F16> {
     uint32_t base;
     uint32_t W[4][3];
     __device__ __forceinline__ float v(int r, int q) const { return dec16<DT_F16>(W[r][q >> 1], q & 1); }
-    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
-        const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
-        W[r][0] = x.w[0];
-        W[r][1] = x.w[1];
-        W[r][2] = x.w[2];
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r, uint64_t lim) {
+        load_row16(V, pt, lim, W[r]);
     }
 };
 
@@ -183,21 +196,19 @@ struct CellCache<DT_BF16> {
     uint32_t base;
     uint32_t W[4][3];
     __device__ __forceinline__ float v(int r, int q) const { return dec16<DT_BF16>(W[r][q >> 1], q & 1); }
-    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r) {
-        const Row16 x = *reinterpret_cast<const Row16*>(V + (uint64_t)pt * 6u);
-        W[r][0] = x.w[0];
-        W[r][1] = x.w[1];
-        W[r][2] = x.w[2];
+    __device__ __forceinline__ void load_row(const char* V, uint32_t pt, int r, uint64_t lim) {
+        load_row16(V, pt, lim, W[r]);
     }
 };
 
 template <int DT>
 __device__ __forceinline__ void ensure(const Geom& g, const char* V, uint32_t base, CellCache<DT>& c) {
     if (c.base != base) {
-        c.load_row(V, base, 0);
-        c.load_row(V, base + g.sy, 1);
-        c.load_row(V, base + g.sz, 2);
-        c.load_row(V, base + g.sy + g.sz, 3);
+        const uint64_t lim = 6ull * (uint64_t)g.sz * (uint64_t)g.n[2] - 16ull;  // 16-bit rows only
+        c.load_row(V, base, 0, lim);
+        c.load_row(V, base + g.sy, 1, lim);
+        c.load_row(V, base + g.sz, 2, lim);
+        c.load_row(V, base + g.sy + g.sz, 3, lim);
         c.base = base;
     }
 }

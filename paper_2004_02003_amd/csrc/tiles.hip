@@ -159,18 +159,19 @@ __device__ __forceinline__ void tile_coords(const Geom& g, const TileGeom& tg, c
 }
 
 // Bucket of each neighbour of tile ts (direction (dx, dy, dz) in -1..1 at
-// index (dz + 1) * 9 + (dy + 1) * 3 + dx + 1; -1 outside the block), looked up
-// by the first 27 threads at the start of a workgroup (in parallel with its
-// other loads).
-__device__ __forceinline__ void neighbour_buckets(const TileGeom& tg, const TileOut& o, const int ts[3], int32_t* s_nb) {
+// index (dz + 1) * 9 + (dy + 1) * 3 + dx + 1; -1 outside the block), loaded
+// by the first 27 threads at the start of a workgroup and kept in a register
+// until the scatter (so the load overlaps the step instead of stalling the
+// first barrier).
+__device__ __forceinline__ int32_t neighbour_bucket(const TileGeom& tg, const TileOut& o, const int ts[3]) {
+    int32_t b = -1;
     if (threadIdx.x < 27) {
         const int d = (int)threadIdx.x;
         const int q[3] = {ts[0] + d % 3 - 1, ts[1] + (d / 3) % 3 - 1, ts[2] + d / 9 - 1};
-        int32_t b = -1;
         if (q[0] >= 0 && q[0] < tg.nt[0] && q[1] >= 0 && q[1] < tg.nt[1] && q[2] >= 0 && q[2] < tg.nt[2])
             b = o.slot_of[q[0] + tg.nt[0] * (q[1] + tg.nt[1] * q[2])];
-        s_nb[d] = b;
     }
+    return b;
 }
 
 // Survivors of one workgroup batch into the buckets of the next step.  A
@@ -178,17 +179,21 @@ __device__ __forceinline__ void neighbour_buckets(const TileGeom& tg, const Tile
 // -1..1) unless it jumped further: ranks per direction from LDS atomics, then
 // one global atomic per (batch, destination tile) reserves the slots.
 // Survivors that jumped further take one global atomic each; slots beyond the
-// bucket's capacity go to the next list.  Block-uniform (barriers inside;
-// s_nb from neighbour_buckets, written before the first barrier).
+// bucket's capacity go to the next list.  Block-uniform (barriers inside);
+// nb: the neighbour bucket of direction threadIdx.x (threads 0..26, from
+// neighbour_bucket), stored to s_nb before the first barrier.
 __device__ __forceinline__ void scatter_block(bool surv, const int ts[3], const int td[3], const PState& st,
                                               uint32_t id, const TileGeom& tg, const TileOut& o, uint32_t* s_hist,
-                                              uint32_t* s_base, const int32_t* s_nb) {
+                                              uint32_t* s_base, int32_t* s_nb, int32_t nb) {
     int dir = 27;
     if (surv) {
         const int dx = td[0] - ts[0], dy = td[1] - ts[1], dz = td[2] - ts[2];
         if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) dir = (dz + 1) * 9 + (dy + 1) * 3 + dx + 1;
     }
-    if (threadIdx.x < 27) s_hist[threadIdx.x] = 0u;
+    if (threadIdx.x < 27) {
+        s_hist[threadIdx.x] = 0u;
+        s_nb[threadIdx.x] = nb;
+    }
     __syncthreads();
     uint32_t rank = 0;
     if (surv && dir < 27) rank = atomicAdd(&s_hist[dir], 1u);
@@ -293,7 +298,7 @@ template <int DT, int MODE, int REC, class CA>
 __device__ __forceinline__ void tile_batch(const TileStepArgs& a, bool alive, const PState& st, uint32_t id,
                                            const int tc[3], const char* V0, const char* V1, CA& A, CA& B,
                                            uint32_t& my_steps, uint32_t& my_surv, uint32_t* s_hist,
-                                           uint32_t* s_base, const int32_t* s_nb) {
+                                           uint32_t* s_base, int32_t* s_nb, int32_t nb) {
     double x[3] = {0.0, 0.0, 0.0};
     int status = S_DEFER;
     if (alive) {
@@ -312,7 +317,7 @@ __device__ __forceinline__ void tile_batch(const TileStepArgs& a, bool alive, co
     my_surv += surv ? 1u : 0u;
     int td[3] = {0, 0, 0};
     if (surv) tile_coords(a.g, a.tg, x, td);
-    scatter_block(surv, tc, td, surv ? pack(x) : st, id, a.tg, a.out, s_hist, s_base, s_nb);
+    scatter_block(surv, tc, td, surv ? pack(x) : st, id, a.tg, a.out, s_hist, s_base, s_nb, nb);
     append_list(defer, st, id, a.list_pos, a.list_id, a.list_count);
 }
 
@@ -416,7 +421,7 @@ __global__ __launch_bounds__(NT) void tile_gather_kernel(const TileStepArgs a) {
     }
     int tc[3], lo[3], ext[3];
     tile_box(a.g, a.tg, t, tc, lo, ext);
-    neighbour_buckets(a.tg, a.out, tc, s_nb);
+    const int32_t nb = neighbour_bucket(a.tg, a.out, tc);
     if (cnt <= NT) sort_rows<NT>(a.tg, tc, threadIdx.x < cnt, st0, id0, s_sort, nw * WAVE);
     const char* V0 = in_global(a.f0);
     const char* V1 = in_global(a.f1);
@@ -431,7 +436,7 @@ __global__ __launch_bounds__(NT) void tile_gather_kernel(const TileStepArgs a) {
             id = a.in_id[bin + i];
         }
         CellCache<DT> A, B;
-        tile_batch<DT, MODE, REC>(a, alive, st, id, tc, V0, V1, A, B, my_steps, my_surv, s_hist, s_base, s_nb);
+        tile_batch<DT, MODE, REC>(a, alive, st, id, tc, V0, V1, A, B, my_steps, my_surv, s_hist, s_base, s_nb, nb);
     }
     add_totals<NT>(my_steps, my_surv, a.psteps, a.live_out, s_red, nw);
 }
@@ -467,7 +472,7 @@ __global__ __launch_bounds__(BLOCK) void tile_stage_kernel(const TileStepArgs a)
     if (cnt == 0) return;
     int tc[3], lo[3], ext[3];
     tile_box(a.g, a.tg, t, tc, lo, ext);
-    neighbour_buckets(a.tg, a.out, tc, s_nb);
+    const int32_t nb = neighbour_bucket(a.tg, a.out, tc);
     {
         SR sr;
         sr.load(a.g, in_global(a.f0), in_global(a.f1), lo, ext);
@@ -494,7 +499,7 @@ __global__ __launch_bounds__(BLOCK) void tile_stage_kernel(const TileStepArgs a)
             id = a.in_id[bin + i];
         }
         tile_batch<DT, MODE, REC>(a, alive, st, id, tc, nullptr, nullptr, A, B, my_steps, my_surv, s_hist, s_base,
-                                  s_nb);
+                                  s_nb, nb);
     }
     add_totals<BLOCK>(my_steps, my_surv, a.psteps, a.live_out, s_red);
 }

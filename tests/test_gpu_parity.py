@@ -134,13 +134,22 @@ def test_streaming_one_call_per_cycle_matches_one_call():
     a = run_gpu(wl.n, dev, s.times, stride=2)
     b = run_gpu(wl.n, dev, s.times, stride=2, chunks=[1] * wl.n_steps)
     c = run_gpu(wl.n, dev, s.times, stride=2, chunks=[7, 33, 10])
-    _, o = oracle_lattice(oracle.Field(wl.n, gr), s.times, wl.n, 2, wl.n_steps)
+    _, o = oracle_lattice(oracle.Field(wl.n, gr), s.times, wl.n, 2, wl.n_steps, jac=True)
+    # Each launch re-rounds the position to the stored state (<= 2^-33 cells),
+    # which can move a later stage point across a cell face, where the FP32
+    # sampler rounds differently: two runs differ by at most twice the
+    # first-order FP32 sampling bound ||J|| N h max|V| 2^-21 (J from the oracle)
+    vmax = float(np.abs(gr).max()) * np.sqrt(3.0)
+    h = float(s.times[1] - s.times[0])
+    tol = 1e-7 + 2.0 * np.linalg.norm(o["jac"], axis=(1, 2), ord=2) * wl.n_steps * h * vmax * 2.0 ** -21
     for r, lab in ((b, "per-cycle"), (c, "ragged chunks")):
         compare(r, o, label=lab)
         amb = o["margin"] < 1e-6
         assert np.array_equal(r["flag"][~amb], a["flag"][~amb])
-        # each launch re-rounds the position to the stored state (<= 2^-33 cells per launch)
-        assert np.abs(r["end"] - a["end"]).max() < 1e-7
+        d = np.abs(r["end"] - a["end"]).max(axis=1)
+        ok = ~amb & (o["flag"] == 0)
+        assert np.all(d[ok] <= tol[ok]), f"{lab}: {d[ok].max():.3e} beyond {tol[ok][np.argmax(d[ok] - tol[ok])]:.3e}"
+        _say(f"{lab}: max |one call - streamed| {d[ok].max():.2e}, median bound {np.median(tol[ok]):.2e}")
 
 
 def test_ragged_block_and_lattice_all_dtypes():
