@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbto.so")
 SOURCES = ["advect.hip", "tiles.hip", "seed_flowmap.hip", "adjoint.hip", "grad_reduce.hip", "rebin.hip", "reconstruct.hip",
-           "touched.hip", "api.hip"]
+           "touched.hip", "radix.hip", "api.hip"]
 ARCH = os.environ.get("BTO_OFFLOAD_ARCH", "gfx950")
 
 

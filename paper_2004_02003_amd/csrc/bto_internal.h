@@ -340,6 +340,16 @@ hipError_t launch_grad_reduce(const GradRec& r, uint64_t n, uint64_t* key_out, u
                               void* temp, size_t temp_bytes, float* const* gf, const Geom& g, hipStream_t s);
 hipError_t launch_ftle(const float* jac, int64_t P, double inv_T, float* out, hipStream_t s);
 size_t rebin_temp_bytes(int64_t nbins_total);
+
+// Device-wide exclusive scan of n counts (in != out; temp: scan_temp_bytes)
+// and stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
+// ping-ponging between (key, val) and (key_alt, val_alt); *result_in_alt says
+// which pair of arrays holds the sorted result (temp: radix_temp_bytes).
+size_t scan_temp_bytes(uint64_t n);
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, void* temp, hipStream_t s);
+size_t radix_temp_bytes(uint64_t n);
+hipError_t launch_radix_sort_pairs(uint64_t* key, uint32_t* val, uint64_t* key_alt, uint32_t* val_alt, uint64_t n,
+                                   int bits, void* temp, bool* result_in_alt, hipStream_t s);
 hipError_t launch_rebin(const RebinArgs& a, hipStream_t s);
 
 }  // namespace bto

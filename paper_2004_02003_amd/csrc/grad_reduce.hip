@@ -3,7 +3,8 @@
 // The reverse sweep writes one record per accumulator flush into a slot fixed
 // by (flush rank, seed): the 8 corner gradients (x 3 components) of one cell
 // of one grid level, keyed by parity colour | level | cell (unused slots carry
-// a key above every colour).  A stable radix sort orders the records by key;
+// a key above every colour).  A stable radix sort (radix.hip) orders the
+// records by key;
 // then, one colour at a time (a contiguous range of the sorted keys), each
 // (level, cell) group is summed in slot order (the flush's rank, then the
 // seed id) and added to the grid's 8 corners with plain loads and stores.
@@ -13,8 +14,6 @@
 // depend on thread timing, unlike FP32 atomics, and each corner costs one
 // read and one write per group instead of one memory-side atomic per
 // contribution.
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include "bto_internal.h"
 
 namespace bto {
@@ -78,13 +77,7 @@ __global__ __launch_bounds__(BLOCK) void grad_apply_kernel(const uint64_t* key, 
 
 static int key_bits(const GradRec& r) { return r.level_bits + r.cell_bits + 3; }
 
-size_t grad_sort_temp_bytes(uint64_t n, int bits) {
-    size_t bytes = 0;
-    if (rocprim::radix_sort_pairs(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint32_t*)nullptr,
-                                  (uint32_t*)nullptr, (size_t)n, 0u, (unsigned)bits) != hipSuccess)
-        return 0;
-    return bytes;
-}
+size_t grad_sort_temp_bytes(uint64_t n, int) { return radix_temp_bytes(n); }
 
 static unsigned grid_of(uint64_t n) {
     const uint64_t b = (n + BLOCK - 1) / BLOCK;
@@ -102,11 +95,17 @@ hipError_t launch_grad_reduce(const GradRec& r, uint64_t n, uint64_t* key_out, u
                               void* temp, size_t temp_bytes, float* const* gf, const Geom& g, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int colour_shift = key_bits(r) - 3;
-    size_t bytes = temp_bytes;
-    // one more bit than the key fields: the unused-slot marker
-    hipError_t e = rocprim::radix_sort_pairs(temp, bytes, r.key, key_out, r.idx, idx_out, (size_t)n, 0u,
-                                             (unsigned)(key_bits(r) + 1), s);
+    (void)temp_bytes;
+    // one more bit than the key fields: the unused-slot marker; the sorted
+    // pairs end in (key_out, idx_out) or, after an even number of passes, in
+    // the records' own arrays
+    bool in_alt = false;
+    hipError_t e = launch_radix_sort_pairs(r.key, r.idx, key_out, idx_out, n, key_bits(r) + 1, temp, &in_alt, s);
     if (e != hipSuccess) return e;
+    if (!in_alt) {
+        key_out = r.key;
+        idx_out = r.idx;
+    }
     hipLaunchKernelGGL(grad_bounds_kernel, dim3(grid_of(n + 1)), dim3(BLOCK), 0, s, key_out, n, colour_shift, bounds);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -10,13 +10,11 @@
 // a counting sort:
 //   count   - per particle, atomically increment its (segment, bin) counter;
 //             the old value is the particle's rank inside the bin;
-//   scan    - exclusive prefix sum over all bins (segment-major);
+//   scan    - exclusive prefix sum over all bins (segment-major; radix.hip);
 //   scatter - move each particle to its segment base + bin offset + rank, and
 //             zero its bin for the next rebin.
 // Order inside a bin is unspecified; results do not depend on particle
 // order.
-#include <rocprim/device/device_scan.hpp>
-
 #include "bto_internal.h"
 
 namespace bto {
@@ -65,22 +63,14 @@ static int grid_of(int64_t n) {
     return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
 }
 
-size_t rebin_temp_bytes(int64_t nbins_total) {
-    size_t bytes = 0;
-    if (rocprim::exclusive_scan(nullptr, bytes, (uint32_t*)nullptr, (uint32_t*)nullptr, 0u,
-                                (size_t)nbins_total, rocprim::plus<uint32_t>()) != hipSuccess)
-        return 0;
-    return bytes;
-}
+size_t rebin_temp_bytes(int64_t nbins_total) { return scan_temp_bytes((uint64_t)nbins_total); }
 
 hipError_t launch_rebin(const RebinArgs& a, hipStream_t s) {
     if (a.P == 0) return hipSuccess;
     hipLaunchKernelGGL(rebin_count_kernel, dim3(grid_of(a.P)), dim3(BLOCK), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t bytes = a.temp_bytes;
-    e = rocprim::exclusive_scan(a.temp, bytes, a.hist, a.offs, 0u, (size_t)NSEG * a.nbins, rocprim::plus<uint32_t>(),
-                                s);
+    e = launch_exclusive_scan(a.hist, a.offs, (uint64_t)NSEG * a.nbins, a.temp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(rebin_scatter_kernel, dim3(grid_of(a.P)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
