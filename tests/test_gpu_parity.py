@@ -475,6 +475,9 @@ def test_error_paths_and_tuning_through_the_c_abi():
             ctx.advect(dev, s.times)
         assert e.value.code == _lib.BTO_ESTATE
         with pytest.raises(BTOError) as e:
+            ctx.touched_points(dev, s.times)
+        assert e.value.code == _lib.BTO_ESTATE and "seeding" in str(e.value)
+        with pytest.raises(BTOError) as e:
             ctx.seed(1)  # 12*10*8 = 960 seeds > capacity 100
         assert e.value.code == _lib.BTO_ERANGE and "capacity" in str(e.value)
         with pytest.raises(BTOError) as e:
@@ -491,6 +494,11 @@ def test_error_paths_and_tuning_through_the_c_abi():
         with pytest.raises(BTOError) as e:
             ctx.advect_ptrs([dev[0].data_ptr(), 0], s.times[:2], 0)
         assert e.value.code == _lib.BTO_EINVAL
+        with pytest.raises(BTOError) as e:
+            ctx.touched_points(dev, [0.0, 1.0, 1.0, 2.0])
+        assert e.value.code == _lib.BTO_EINVAL and "increasing" in str(e.value)
+        t = ctx.touched_points(dev, s.times)  # a diagnostic walk: the interval is not advanced
+        assert t.shape == (3, 3) and int(t[0, 2]) == P and ctx.stats()["steps_done"] == 0
         with pytest.raises(BTOError) as e:
             ctx.set_tuning(steps_per_launch=0)
         assert e.value.code == _lib.BTO_EINVAL
