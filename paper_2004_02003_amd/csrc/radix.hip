@@ -31,9 +31,9 @@ static_assert(RADIX_BINS % BLOCK == 0, "whole digits per thread");
 // ---------------------------------------------------------------------------
 // Scan.
 // ---------------------------------------------------------------------------
-// Exclusive scan of one 4,096-count chunk by one workgroup (in may equal out);
-// the chunk's total goes to totals[chunk] (if non-null); add: an offset per
-// chunk (or null).
+// Exclusive scan of one 4,096-count chunk by one workgroup; the chunk's total
+// goes to totals[chunk] (if non-null); add: an offset per chunk (or null).
+// launch_exclusive_scan reads `in` twice, so in and out must not overlap.
 __global__ __launch_bounds__(BLOCK) void scan_chunk_kernel(const uint32_t* in, uint32_t* out, uint64_t n,
                                                            uint32_t* totals, const uint32_t* add) {
     __shared__ uint32_t s_wave[BLOCK / WAVE];
@@ -116,8 +116,8 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, 
         hipLaunchKernelGGL(scan_chunk_kernel, dim3(1), dim3(BLOCK), 0, s, in, out, n, nullptr, nullptr);
         return hipGetLastError();
     }
-    // totals first (a reduce pass: the chunk scan with its output discarded
-    // would need a second buffer, so scan into out and rescan below)
+    // chunk totals first (the chunk-local scans written to out by this pass
+    // are rewritten with their offsets by the third pass)
     hipLaunchKernelGGL(scan_chunk_kernel, dim3((unsigned)chunks), dim3(BLOCK), 0, s, in, out, n, totals, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
