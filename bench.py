@@ -15,7 +15,9 @@ flow-map write, median of HIP-event times over the timed intervals; grid
 generation excluded and reported on its own), the roofline of the dominant
 kernel at the per-unit figure of two grid levels over 8 points plus 40 bytes
 of particle state per live particle-step (136 B for 16-bit storage, 232 B for
-FP32), and the FP64 oracle timed on the host cores.
+FP32), and the CPU baseline leg: the FP64 oracle timed on the host cores, and
+(with the other legs) the oracle's FP64 references for the stated error of
+the GPU path.  The oracle runs in that leg only.
 """
 
 from __future__ import annotations
@@ -254,19 +256,17 @@ def insitu_overlap(log, n=128, modes=32):
 UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 
 
-def precision_statement(log, threads):
-    """End-position error of the GPU path against the FP64 oracle on the FP64
-    field, per storage type, for the turbulence blocks: the 256^3 precision
-    workload in f32/f16/bf16 on every 509th seed (4,121 seeds), and the 512^3
-    scale workload in f16 on 65,536 seeds (one per lattice row, spread over
-    x), both through a two-slot ring with one call per cycle.  Mean, p99 and max over the seeds
-    valid on both sides, the share beyond 1e-5 cells, and the first-order bound
-    ||J|| N h max|V| sqrt(3) (u_storage + 2^-21) per seed (J from the oracle's
-    FP64 tangent, u the storage's unit roundoff, 2^-21 the FP32 sampling)."""
+def precision_gpu_runs(log):
+    """The GPU side of the stated error (the oracle side is in the CPU
+    baseline leg, cpu_reference_errors): end positions and flags of sampled
+    seeds of the turbulence blocks, per storage type, through a two-slot ring
+    with one call per cycle -- the 256^3 precision workload in f32 (FP32 and
+    FP64 sampling), f16 and bf16 on every 509th seed (4,121 seeds), and the
+    512^3 scale workload in f16 on 65,536 seeds (one per lattice row, spread
+    over x) -- with the largest velocity magnitude of the grids read."""
     import torch
-    import oracle
     from bto_inputs import _turb
-    from bto_inputs.workloads import WORKLOADS, lattice_dims, row_sample_ids
+    from bto_inputs.workloads import WORKLOADS, lattice_dims, lattice_points, row_sample_ids
     from paper_2004_02003_amd import Context
 
     out = {}
@@ -279,15 +279,10 @@ def precision_statement(log, threads):
             ids = row_sample_ids(lattice_dims(wl.n, wl.stride), wl.n_seeds // every)
         else:
             ids = np.arange(0, wl.n_seeds, every)
-        seeds = oracle.seed_lattice(wl.n, wl.stride)[ids]
-        t0 = time.perf_counter()
-        o = oracle.flowmap(oracle.Field.lazy_turbulence(s, "f64"), s.times, seeds, N, jac=True, nthreads=threads)
-        log(f"precision {name}: FP64 oracle on {len(ids)} seeds in {time.perf_counter() - t0:.1f} s")
-        nJ = np.linalg.norm(o["jac"], axis=(1, 2), ord=2)
-        res = {}
         runs = [(dt, dt, False) for dt in wl.dtypes]
         if "f32" in wl.dtypes:
             runs.insert(1, ("f32_sampled_fp64", "f32", True))
+        res = {}
         for key, dt, fp64 in runs:
             vmax = 0.0
             ring = Ring(gen, wl.n, dt)
@@ -303,24 +298,14 @@ def precision_statement(log, threads):
                     p_prev = p_next
                 fm = ctx.flowmap()
                 torch.cuda.synchronize()
-                end = fm["end"].cpu().numpy()[ids]
-                flag = fm["flag"].cpu().numpy()[ids]
+                res[key] = dict(end=fm["end"].cpu().numpy()[ids], flag=fm["flag"].cpu().numpy()[ids], vmax=vmax,
+                                dt=dt, fp64=fp64)
             del ring
             torch.cuda.empty_cache()
-            both = (flag == 0) & (o["flag"] == 0)
-            err = np.linalg.norm(end[both] - o["end"][both], axis=1)
-            bound = nJ[both] * N * wl.dt * vmax * np.sqrt(3.0) * (UNIT_ROUNDOFF[dt] + (2.0 ** -50 if fp64 else 2.0 ** -21))
-            safe = o["margin"] >= 1e-6
-            res[key] = {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
-                       "n": int(both.sum()), "beyond_1e-5_pct": round(100.0 * float((err > 1e-5).mean()), 3),
-                       "within_first_order_bound_pct": round(100.0 * float((err <= bound).mean()), 2),
-                       "bound_median": float(np.median(bound)),
-                       "flag_disagree": int((flag != o["flag"]).sum()),
-                       "flag_disagree_outside_margin": int(((flag != o["flag"]) & safe).sum())}
-            log(f"precision {name} {key}: {res[key]}")
+        log(f"precision {name}: GPU runs of {len(ids)} sampled seeds done")
         pick = "one per lattice row, x index cycling" if every == 256 else f"every {every}th"
-        out[name] = {"seeds": f"{pick} of {wl.n_seeds} ({len(ids)})", "steps": N,
-                     "cells": "end-position L2 error, cells", **res}
+        out[name] = dict(wl=wl, series=s, ids=ids, seeds=lattice_points(wl.n, wl.stride, ids), runs=res,
+                         label=f"{pick} of {wl.n_seeds} ({len(ids)})")
     return out
 
 
@@ -506,8 +491,7 @@ def differentiation(log):
 LEGS = {
     "turb_256_storage": lambda log, copy_gbs: turb_storage_legs(log, copy_gbs),
     "abc_128": lambda log, copy_gbs: abc_128_leg(log, copy_gbs),
-    "precision_turbulence": lambda log, copy_gbs: precision_statement(
-        log, int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()),
+    "precision_turbulence": lambda log, copy_gbs: precision_leg(log),
     "paper_context": lambda log, copy_gbs: paper_context(log),
     "posthoc_accuracy": lambda log, copy_gbs: posthoc_accuracy(log),
     "insitu_overlap": lambda log, copy_gbs: [insitu_overlap(log, 128, 32), insitu_overlap(log, 256, 64)],
@@ -859,6 +843,49 @@ def cpu_baseline_of(wl, series, dt, turb, grids_host, log, target_s=10.0):
     return res, one
 
 
+def cpu_reference_errors(gpu, threads, log):
+    """The oracle side of the stated error (part of the CPU baseline leg: the
+    only bench step that runs the oracle).  For each sampled seed of
+    precision_gpu_runs: the FP64 oracle on the FP64 field with its tangent,
+    then per storage type the end-position error of the GPU path (mean, p99,
+    max over the seeds valid on both sides, the share beyond 1e-5 cells) and
+    the first-order bound ||J|| N h max|V| sqrt(3) (u_storage + 2^-21) per seed
+    (J from the oracle's tangent, u the storage's unit roundoff, 2^-21 the FP32
+    sampling, 2^-50 with FP64 sampling)."""
+    import oracle
+
+    out = {}
+    for name, g in gpu.items():
+        wl, s = g["wl"], g["series"]
+        N = wl.n_steps
+        t0 = time.perf_counter()
+        o = oracle.flowmap(oracle.Field.lazy_turbulence(s, "f64"), s.times, g["seeds"], N, jac=True, nthreads=threads)
+        log(f"precision {name}: FP64 oracle on {len(g['ids'])} seeds in {time.perf_counter() - t0:.1f} s")
+        nJ = np.linalg.norm(o["jac"], axis=(1, 2), ord=2)
+        safe = o["margin"] >= 1e-6
+        res = {}
+        for key, r in g["runs"].items():
+            end, flag = r["end"], r["flag"]
+            both = (flag == 0) & (o["flag"] == 0)
+            err = np.linalg.norm(end[both] - o["end"][both], axis=1)
+            bound = (nJ[both] * N * wl.dt * r["vmax"] * np.sqrt(3.0) *
+                     (UNIT_ROUNDOFF[r["dt"]] + (2.0 ** -50 if r["fp64"] else 2.0 ** -21)))
+            res[key] = {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
+                        "n": int(both.sum()), "beyond_1e-5_pct": round(100.0 * float((err > 1e-5).mean()), 3),
+                        "within_first_order_bound_pct": round(100.0 * float((err <= bound).mean()), 2),
+                        "bound_median": float(np.median(bound)),
+                        "flag_disagree": int((flag != o["flag"]).sum()),
+                        "flag_disagree_outside_margin": int(((flag != o["flag"]) & safe).sum())}
+            log(f"precision {name} {key}: {res[key]}")
+        out[name] = {"seeds": g["label"], "steps": N, "cells": "end-position L2 error, cells", **res}
+    return out
+
+
+def precision_leg(log):
+    gpu = precision_gpu_runs(log)
+    return cpu_reference_errors(gpu, int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count(), log)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -960,12 +987,16 @@ def main(argv=None):
     if not args.no_variants:
         result["turb_256_storage"] = turb_storage_legs(log, copy_gbs)
         result["abc_128"] = abc_128_leg(log, copy_gbs)
-        result["precision_turbulence"] = precision_statement(log, int(os.environ.get("OMP_NUM_THREADS", "0"))
-                                                             or os.cpu_count())
+        precision_gpu = precision_gpu_runs(log)
         result["differentiation"] = differentiation(log)
         result["paper_context"] = paper_context(log)
     if not args.no_cpu_baseline:
+        # the CPU baseline leg: the oracle timed on a bounded sample, and (with
+        # the legs) the oracle's FP64 references for the stated error
         result["cpu_baseline"], result["cpu_baseline_1thread"] = cpu_baseline_of(wl, series, dt, True, None, log)
+        if not args.no_variants:
+            result["precision_turbulence"] = cpu_reference_errors(
+                precision_gpu, int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count(), log)
 
     if args.copy_probe:
         x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")

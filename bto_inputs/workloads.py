@@ -90,6 +90,16 @@ def lattice_dims(n, stride: int):
     return tuple(int((int(nd) - 1 - off) // stride) + 1 for nd in n)
 
 
+def lattice_points(n, stride: int, ids) -> np.ndarray:
+    """Cell coordinates of the lattice seeds with the given ids: off + stride*k
+    per axis (off = (stride-1)/2), ids x-fastest over lattice_dims(n, stride)."""
+    m = lattice_dims(n, stride)
+    ids = np.asarray(ids, dtype=np.int64)
+    off = (stride - 1) / 2.0
+    k = np.stack([ids % m[0], (ids // m[0]) % m[1], ids // (m[0] * m[1])], axis=1)
+    return off + stride * k.astype(np.float64)
+
+
 def row_sample_ids(m, count: int) -> np.ndarray:
     """Ids of ``count`` seeds of an x-fastest lattice of m = (mx, my, mz)
     seeds, spread over the block: the chosen rows (y, z) are every

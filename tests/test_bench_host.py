@@ -48,7 +48,7 @@ def test_launch_shapes_and_tables_are_consistent(bench):
                 assert shape.get("lanes_per_particle", 1) == 1 or dt == "f32"
     assert set(bench.PAPER_ABC_TABLE_MS) == {(i, s) for i in (25, 50, 100) for s in (1, 2, 3)}
     assert set(bench.UNIT_ROUNDOFF) == {"f32", "f16", "bf16"}
-    for fn in ("paper_context", "posthoc_accuracy", "insitu_overlap", "precision_statement", "differentiation",
+    for fn in ("paper_context", "posthoc_accuracy", "insitu_overlap", "precision_gpu_runs", "cpu_reference_errors", "differentiation",
                "per_cycle", "kernel_hash", "main", "insitu_measure", "run_insitu_interval", "turb_storage_legs",
                "abc_128_leg", "cpu_baseline_of", "roofline_of"):
         assert callable(getattr(bench, fn)), fn
@@ -73,11 +73,15 @@ def test_seed_subsets_spread_over_the_lattice():
     import numpy as np
 
     import oracle
-    from bto_inputs.workloads import lattice_dims, row_sample_ids
+    from bto_inputs.workloads import lattice_dims, lattice_points, row_sample_ids
 
     for n, stride in (((37, 23, 19), 3), ((40, 30, 20), 2), ((16, 16, 16), 4)):
         m = lattice_dims(n, stride)
-        assert int(np.prod(m)) == len(oracle.seed_lattice(n, stride))
+        lat = oracle.seed_lattice(n, stride)
+        assert int(np.prod(m)) == len(lat)
+        ids = np.arange(len(lat))
+        assert np.array_equal(lattice_points(n, stride, ids), lat)
+        assert np.array_equal(lattice_points(n, stride, ids[::7]), lat[::7])
     m = (256, 256, 256)
     ids = row_sample_ids(m, 65536)
     assert len(ids) == 65536 and len(np.unique(ids)) == 65536 and ids.max() < 256 ** 3
