@@ -202,7 +202,8 @@ int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
  *                       tiles in Morton order with one eighth of them per
  *                       XCD; each survivor goes into the bucket of the tile it
  *                       ends in, so the particles stay sorted by tile.  With 2
- *                       (12^3-cell tiles) the particles gather from the grids.
+ *                       (tiles of 32 x 8 x 8 cells, long along x) the
+ *                       particles gather from the grids.
  *                       With 1 the workgroup first stages its tile's cells
  *                       plus a 2-cell halo of both grid levels in LDS with
  *                       coalesced loads and samples from there (12^3-cell

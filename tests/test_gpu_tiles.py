@@ -110,8 +110,9 @@ def test_tiles_ragged_block_stride_3_and_streaming():
 
 
 def test_tiles_crowded_seeds_overflow_their_buckets():
-    # 6,000 seeds in a 3x3x3-cell corner of one 12^3 tile: the bucket capacity
-    # (twice the mean per tile plus 32) is exceeded, the rest waits in the list
+    # 6,000 seeds in a 3x3x3-cell region that at most four gathering tiles
+    # (32 x 8 x 8 cells) or one staged tile share: the bucket capacity (twice
+    # the mean per tile plus 32) is exceeded, the rest waits in the list
     rng = np.random.default_rng(5)
     n = (40, 40, 40)
     N = 10
