@@ -694,9 +694,9 @@ def turb_storage_legs(log, copy_gbs, steps=3, warmup=1):
             rec = {"value": round(m["particle_steps"] / (m["interval_ms_median"] * 1e-3), 1),
                    "interval_ms": round(m["interval_ms_median"], 4), "particle_steps": m["particle_steps"],
                    "valid_at_end": m["valid_at_end"],
-                   "roofline": roofline_of(m, dt, wl.name, "insitu",
-                                           f"tile_gather_kernel<{dt},linear> + tile_list_kernel (one step per call)",
-                                           copy_gbs),
+                   "roofline": roofline_of(m, dt, wl.name, "insitu_fp64" if fp64 else "insitu",
+                                           f"tile_gather_kernel<{dt},linear{',fp64 sampling' if fp64 else ''}> + "
+                                           f"tile_list_kernel (one step per call)", copy_gbs),
                    "tuning": m["tuning"]}
             # fused: all grids resident, several steps per launch (segment layout,
             # latched at the next seeding)
