@@ -37,8 +37,10 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-RK4-steps/s on 1 MI355X + %HBM peak; FP32 vs FP16 field at stated err"
 HBM_PEAK_GBS = 8000.0
 STATE_BYTES = 40          # 16 B state + 4 B id, read once and written once per launch
+# the dominant kernels and the host code that sets their launch order and buffers
 KERNEL_SOURCES = ["paper_2004_02003_amd/csrc/bto_device.h", "paper_2004_02003_amd/csrc/bto_internal.h",
-                  "paper_2004_02003_amd/csrc/advect.hip", "paper_2004_02003_amd/csrc/tiles.hip"]
+                  "paper_2004_02003_amd/csrc/advect.hip", "paper_2004_02003_amd/csrc/tiles.hip",
+                  "paper_2004_02003_amd/csrc/api.hip"]
 
 
 def kernel_hash() -> str:

@@ -262,9 +262,9 @@ static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hip
 // ---------------------------------------------------------------------------
 // Tile layout.
 // ---------------------------------------------------------------------------
-static uint32_t spread3(uint32_t v) {  // bits of v at every third position
-    uint32_t r = 0;
-    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+static uint64_t spread3(uint32_t v) {  // bits of v (up to 21) at every third position
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= (uint64_t)((v >> b) & 1u) << (3 * b);
     return r;
 }
 
@@ -294,14 +294,20 @@ static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
         c->tcap == (uint32_t)cap)
         return BTO_OK;
     // workgroup order: all tiles in Morton order, cut into NSEG equal
-    // contiguous runs, run x for XCD x; order[k * NSEG + x] = k-th tile of run x
+    // contiguous runs, run x for XCD x; order[k * NSEG + x] = k-th tile of run x.
+    // The curve runs in cell space: a tile's coordinates are scaled by its
+    // side over the shortest side, so a run of the curve is a compact region
+    // of cells even for tiles long along x (3% on the 512^3 f16 step).
+    const int tmin = std::min(tg.T[0], std::min(tg.T[1], tg.T[2]));
     std::vector<std::pair<uint64_t, int32_t>> mt;
     mt.reserve((size_t)ntiles);
     for (int tz = 0; tz < tg.nt[2]; ++tz)
         for (int ty = 0; ty < tg.nt[1]; ++ty)
             for (int tx = 0; tx < tg.nt[0]; ++tx) {
-                const uint64_t key = (uint64_t)spread3((uint32_t)tx) | ((uint64_t)spread3((uint32_t)ty) << 1) |
-                                     ((uint64_t)spread3((uint32_t)tz) << 2);
+                const uint32_t px = (uint32_t)(tx * (tg.T[0] / tmin)), py = (uint32_t)(ty * (tg.T[1] / tmin)),
+                               pz = (uint32_t)(tz * (tg.T[2] / tmin));
+                const uint64_t key = (uint64_t)spread3(px) | ((uint64_t)spread3(py) << 1) |
+                                     ((uint64_t)spread3(pz) << 2);
                 mt.push_back({key, tx + tg.nt[0] * (ty + tg.nt[1] * tz)});
             }
     std::sort(mt.begin(), mt.end());
