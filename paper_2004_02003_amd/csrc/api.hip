@@ -262,10 +262,35 @@ static int start_interval(bto_ctx* c, int64_t P, const uint32_t* seg_counts, hip
 // ---------------------------------------------------------------------------
 // Tile layout.
 // ---------------------------------------------------------------------------
-static uint64_t spread3(uint32_t v) {  // bits of v (up to 21) at every third position
-    uint64_t r = 0;
-    for (int b = 0; b < 21; ++b) r |= (uint64_t)((v >> b) & 1u) << (3 * b);
-    return r;
+// Index of (x, y, z) along a 3-D Hilbert curve over [0, 2^bits)^3, in
+// Skilling's transpose form ("Programming the Hilbert curve", 2004): undo the
+// excess work of the axes from the top bit down, Gray-encode across the axes,
+// then interleave the bits from the most significant.  Consecutive indices
+// are unit steps in space.
+static uint64_t hilbert3(uint32_t x, uint32_t y, uint32_t z, int bits) {
+    uint32_t X[3] = {x, y, z};
+    const uint32_t M = 1u << (bits - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint64_t h = 0;
+    for (int j = bits - 1; j >= 0; --j)
+        for (int i = 0; i < 3; ++i) h = (h << 1) | ((X[i] >> j) & 1u);
+    return h;
 }
 
 
@@ -293,12 +318,17 @@ static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
     if (c->tile_buf && std::memcmp(&c->tg, &tg, sizeof tg) == 0 && c->ntiles == (uint32_t)ntiles &&
         c->tcap == (uint32_t)cap)
         return BTO_OK;
-    // workgroup order: all tiles in Morton order, cut into NSEG equal
+    // workgroup order: all tiles along a Hilbert curve, cut into NSEG equal
     // contiguous runs, run x for XCD x; order[k * NSEG + x] = k-th tile of run x.
     // The curve runs in cell space: a tile's coordinates are scaled by its
     // side over the shortest side, so a run of the curve is a compact region
-    // of cells even for tiles long along x (3% on the 512^3 f16 step).
+    // of cells even for tiles long along x (on the 512^3 f16 step: Morton
+    // order on tile indices 0.877 ms, Morton in cell space 0.833 ms, Hilbert
+    // in cell space 0.823 ms).
     const int tmin = std::min(tg.T[0], std::min(tg.T[1], tg.T[2]));
+    int hbits = 1;
+    for (int d = 0; d < 3; ++d)
+        while ((1u << hbits) < (uint32_t)(tg.nt[d] * (tg.T[d] / tmin))) ++hbits;
     std::vector<std::pair<uint64_t, int32_t>> mt;
     mt.reserve((size_t)ntiles);
     for (int tz = 0; tz < tg.nt[2]; ++tz)
@@ -306,8 +336,7 @@ static int tile_setup(bto_ctx* c, int dtype, hipStream_t s) {
             for (int tx = 0; tx < tg.nt[0]; ++tx) {
                 const uint32_t px = (uint32_t)(tx * (tg.T[0] / tmin)), py = (uint32_t)(ty * (tg.T[1] / tmin)),
                                pz = (uint32_t)(tz * (tg.T[2] / tmin));
-                const uint64_t key = (uint64_t)spread3(px) | ((uint64_t)spread3(py) << 1) |
-                                     ((uint64_t)spread3(pz) << 2);
+                const uint64_t key = hilbert3(px, py, pz, hbits);
                 mt.push_back({key, tx + tg.nt[0] * (ty + tg.nt[1] * tz)});
             }
     std::sort(mt.begin(), mt.end());
