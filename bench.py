@@ -729,7 +729,7 @@ def turb_storage_legs(log, copy_gbs, steps=3, warmup=1):
 
 # Launch shape per workload and storage (results do not depend on it).
 # In situ (one step per call) the turbulent blocks keep their particles in
-# the tile layout, sorted by tile (32 x 8 x 8 cells) and run in Morton tile order (the
+# the tile layout, sorted by tile (32 x 8 x 8 cells) and run in Hilbert tile order (the
 # particles mix at 1.5 cells per step; the tile order keeps the grid lines a
 # tile's particles read in L2 for its neighbours).  Fused (all grids
 # resident, several steps per launch) they re-sort every few steps, and for

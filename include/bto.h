@@ -199,8 +199,8 @@ int bto_stats(bto_ctx *ctx, bto_stats_t *out, void *stream);
  *   tiles               0 (default), 1 or 2.  With 1 or 2, every RK4 step is
  *                       its own pair of launches over the live particles kept
  *                       in buckets by tile of cells, one workgroup per tile,
- *                       tiles in Morton order with one eighth of them per
- *                       XCD; each survivor goes into the bucket of the tile it
+ *                       tiles along a Hilbert curve in cell space with one
+ *                       eighth of them per XCD; each survivor goes into the bucket of the tile it
  *                       ends in, so the particles stay sorted by tile.  With 2
  *                       (tiles of 32 x 8 x 8 cells, long along x) the
  *                       particles gather from the grids.

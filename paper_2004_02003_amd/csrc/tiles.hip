@@ -1,10 +1,10 @@
 // Tile layout of the live particles: the in situ step in tile order.
 //
-// Live particles are kept in buckets, one per tile of T x T x T cells (a
-// particle belongs to the tile of its sampling cell); tiles run in Morton
-// order, one eighth of them per XCD, so neighbouring tiles run close in time
-// on one XCD and share the grid lines of their common faces in its L2.  One
-// step is two launches:
+// Live particles are kept in buckets, one per tile of cells (a particle
+// belongs to the tile of its sampling cell); tiles run along a Hilbert curve
+// in cell space, one eighth of the curve per XCD, so neighbouring tiles run
+// close in time on one XCD and share the grid lines of their common faces in
+// its L2.  One step is two launches:
 //   tile_gather_kernel  one workgroup per tile: advance every particle of the
 //   (tiles = 2)         tile one RK4 step, gathering the grid values, and
 //                       write each survivor into the bucket of the tile it
