@@ -24,9 +24,9 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
     const bool owner = half == 0;  // the lane that writes the particle's results
     __shared__ uint32_t s_cnt[W];
     __shared__ uint32_t s_base;
-    if (blockIdx.x == 0 && threadIdx.x < NSEG) a.clear_count[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < NSEG) a.clear_count[threadIdx.x * CSTRIDE] = 0u;
 
-    const uint32_t cnt = a.in_count[seg];
+    const uint32_t cnt = a.in_count[seg * CSTRIDE];
     const int64_t sbase = a.segs.base[seg];
     uint32_t my_steps = 0;
 
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
                 s_cnt[w] = tot;
                 tot += c;
             }
-            s_base = tot ? atomicAdd(&a.out_count[seg], tot) : 0u;
+            s_base = tot ? atomicAdd(&a.out_count[seg * CSTRIDE], tot) : 0u;
         }
         __syncthreads();
         if (keep && owner) {
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(BLOCK) void advect_kernel(const AdvectArgs a) {
         unsigned long long tot = 0;
 #pragma unroll
         for (int w = 0; w < W; ++w) tot += s_cnt[w];
-        if (tot) atomicAdd(&a.psteps[seg], tot);
+        if (tot) atomicAdd(&a.psteps[seg * PSTRIDE], tot);
     }
 }
 

@@ -18,6 +18,9 @@
 
 using namespace bto;
 
+// the three slots of live counts, ahead of the particle-step counters
+static constexpr size_t COUNT_BYTES = 3 * NSEG * CSTRIDE * sizeof(uint32_t);
+
 struct bto_ctx {
     bto_block blk;
     Geom geom;
@@ -45,6 +48,7 @@ struct bto_ctx {
     float4* rec_out = nullptr;        // terminated particles: outside point - last inside position
     double* seed_xyz = nullptr;
     // counters: ring of 3 x NSEG live counts, then NSEG particle-step counters
+    // (each counter in a line of its own: CSTRIDE, PSTRIDE)
     uint32_t* counts = nullptr;
     unsigned long long* psteps = nullptr;
     int slot = 0;           // ring slot holding the current live counts
@@ -193,14 +197,13 @@ int bto_create(const bto_block* blk, int64_t max_particles, int32_t device, bto_
     ok = ok && hipMalloc(&c->rec_meta, P * sizeof(int32_t)) == hipSuccess;
     ok = ok && hipMalloc(&c->rec_out, P * sizeof(float4)) == hipSuccess;
     ok = ok && hipMalloc(&c->seed_xyz, P * 3 * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&c->counts, 3 * NSEG * sizeof(uint32_t) + 32 + NSEG * sizeof(unsigned long long)) == hipSuccess;
+    ok = ok && hipMalloc(&c->counts, COUNT_BYTES + NSEG * PSTRIDE * sizeof(unsigned long long)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         bto_destroy(c);
         return BTO_ENOMEM;
     }
-    c->psteps = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(c->counts) + 3 * NSEG * sizeof(uint32_t) +
-                                                      32);
+    c->psteps = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(c->counts) + COUNT_BYTES);
     *out = c;
     return BTO_OK;
 }
@@ -403,7 +406,7 @@ static int tile_enter(bto_ctx* c, int dtype, int max_seg_blocks, hipStream_t s) 
     a.g = c->geom;
     a.tg = c->tg;
     a.segs = c->segs;
-    a.count = c->counts + NSEG * c->slot;
+    a.count = c->counts + NSEG * CSTRIDE * c->slot;
     a.pos = c->pos[c->cur];
     a.id = c->id[c->cur];
     c->tb = 0;
@@ -483,8 +486,8 @@ static int tile_step(bto_ctx* c, const void* f0, const void* f1, double h, int d
     a.rec_meta = c->rec_meta;
     a.rec_out = c->rec_out;
     a.psteps = c->psteps;
-    a.live_out = c->counts + NSEG * sl1;
-    a.live_clear = c->counts + NSEG * sl2;
+    a.live_out = c->counts + NSEG * CSTRIDE * sl1;
+    a.live_clear = c->counts + NSEG * CSTRIDE * sl2;
     hipError_t e = launch_tile_step(a, dtype, mode, rec, c->tiles == 1 ? 1 : 0, s);
     if (e != hipSuccess) return hip_fail(c, e, "tile step launch");
     TileListArgs l{};
@@ -553,7 +556,7 @@ static int rebin(bto_ctx* c, hipStream_t s) {
     RebinArgs a{};
     a.P = c->n_seeds;
     a.segs = c->segs;
-    a.count = c->counts + NSEG * c->slot;
+    a.count = c->counts + NSEG * CSTRIDE * c->slot;
     a.pos = c->pos[c->cur];
     a.id = c->id[c->cur];
     a.out_pos = c->pos[1 - c->cur];
@@ -748,7 +751,7 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
         if (store_ck && c->steps_done % c->ck_k == 0) {
             CkptArgs ca{};
             ca.segs = c->segs;
-            ca.count = c->counts + NSEG * c->slot;
+            ca.count = c->counts + NSEG * CSTRIDE * c->slot;
             ca.pos = c->pos[c->cur];
             ca.id = c->id[c->cur];
             ca.out = c->ck_rec + (size_t)(c->steps_done / c->ck_k) * (size_t)c->cap * 3;
@@ -766,9 +769,9 @@ int bto_advect_interval(bto_ctx* c, const void* const* d_fields, const double* t
         a.in_id = c->id[c->cur];
         a.out_pos = c->pos[1 - c->cur];
         a.out_id = c->id[1 - c->cur];
-        a.in_count = c->counts + NSEG * c->slot;
-        a.out_count = c->counts + NSEG * ((c->slot + 1) % 3);
-        a.clear_count = c->counts + NSEG * ((c->slot + 2) % 3);
+        a.in_count = c->counts + NSEG * CSTRIDE * c->slot;
+        a.out_count = c->counts + NSEG * CSTRIDE * ((c->slot + 1) % 3);
+        a.clear_count = c->counts + NSEG * CSTRIDE * ((c->slot + 2) % 3);
         a.rec_pos = c->rec_pos;
         a.rec_meta = c->rec_meta;
         a.rec_out = c->rec_out;
@@ -796,7 +799,7 @@ int bto_flowmap_out(bto_ctx* c, double* d_seed_xyz, double* d_end_xyz, uint8_t* 
         a.P = c->n_seeds;
         a.steps_done = c->steps_done;
         a.segs = c->segs;
-        a.count = c->counts + NSEG * c->slot;
+        a.count = c->counts + NSEG * CSTRIDE * c->slot;
         a.pos = c->pos[c->cur];
         a.id = c->id[c->cur];
         a.rec_pos = c->rec_pos;
@@ -923,16 +926,16 @@ int bto_stats(bto_ctx* c, bto_stats_t* out, void* stream) {
     out->steps_done = c->steps_done;
     if (!c->seeded) return BTO_OK;
     hipStream_t s = (hipStream_t)stream;
-    uint32_t cnt[NSEG];
-    unsigned long long psv[NSEG];
-    hipError_t e = hipMemcpyAsync(cnt, c->counts + NSEG * c->slot, sizeof cnt, hipMemcpyDeviceToHost, s);
+    uint32_t cnt[NSEG * CSTRIDE];
+    unsigned long long psv[NSEG * PSTRIDE];
+    hipError_t e = hipMemcpyAsync(cnt, c->counts + NSEG * CSTRIDE * c->slot, sizeof cnt, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(psv, c->psteps, sizeof psv, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "stats readback");
     int64_t live = 0;
-    for (int x = 0; x < NSEG; ++x) live += cnt[x];
+    for (int x = 0; x < NSEG; ++x) live += cnt[x * CSTRIDE];
     unsigned long long ps = 0;
-    for (int x = 0; x < NSEG; ++x) ps += psv[x];
+    for (int x = 0; x < NSEG; ++x) ps += psv[x * PSTRIDE];
     out->n_live = live;
     out->particle_steps = (int64_t)ps;
     return BTO_OK;

@@ -8,6 +8,14 @@
 
 namespace bto {
 
+// Per-segment counters (live counts, particle-step totals) lie one 128-byte
+// line apart, counter x of a slot at index x * CSTRIDE (32-bit) or x * PSTRIDE
+// (64-bit).  Every workgroup of a launch adds into them; device-scope atomics
+// are carried out at the memory side, and spreading the counters over lines
+// lets the segments' atomics proceed in parallel there.
+constexpr int CSTRIDE = 32;
+constexpr int PSTRIDE = 16;
+
 // Live particles are split into NSEG contiguous segments of the ping-pong
 // buffers.  Workgroup b of a launch works on segment b % NSEG: consecutive
 // workgroups are dispatched round-robin over the 8 XCDs, so each XCD keeps

@@ -29,7 +29,7 @@ __device__ __forceinline__ int segment_of(const Segs& sg, int64_t i) {
 __global__ __launch_bounds__(BLOCK) void rebin_count_kernel(const RebinArgs a) {
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.P; i += (int64_t)gridDim.x * BLOCK) {
         const int seg = segment_of(a.segs, i);
-        if (i - a.segs.base[seg] >= (int64_t)a.count[seg]) continue;  // slot beyond the segment's live count
+        if (i - a.segs.base[seg] >= (int64_t)a.count[seg * CSTRIDE]) continue;  // slot beyond the segment's live count
         const uint32_t c = a.pos[i].cell;
         const uint32_t key = (c & 1023u) / REBIN_BIN[0] +
                              a.nbx * (((c >> 10) & 1023u) / REBIN_BIN[1] + a.nby * (((c >> 20) & 1023u) / REBIN_BIN[2]));
@@ -45,11 +45,11 @@ __global__ __launch_bounds__(BLOCK) void rebin_scatter_kernel(const RebinArgs a)
 #pragma unroll
     for (int x = 0; x < NSEG; ++x) {
         start[x] = acc;
-        acc += a.count[x];
+        acc += a.count[x * CSTRIDE];
     }
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.P; i += (int64_t)gridDim.x * BLOCK) {
         const int seg = segment_of(a.segs, i);
-        if (i - a.segs.base[seg] >= (int64_t)a.count[seg]) continue;
+        if (i - a.segs.base[seg] >= (int64_t)a.count[seg * CSTRIDE]) continue;
         const uint32_t bin = a.bin[i];
         const int64_t dst = a.segs.base[seg] + (int64_t)(a.offs[bin] - start[seg]) + a.rank[i];
         a.out_pos[dst] = a.pos[i];

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(BLOCK) void seed_explicit_kernel(const SeedExplicit
             const int lseg = __shfl(seg, leader);
             const unsigned long long same = __ballot(in && seg == lseg) & pending;
             uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&a.count[lseg], (uint32_t)__popcll(same));
+            if (lane == leader) base = atomicAdd(&a.count[lseg * CSTRIDE], (uint32_t)__popcll(same));
             base = __shfl(base, leader);
             if (in && seg == lseg) k = base + (uint32_t)__popcll(same & below);
             pending &= ~same;
@@ -114,8 +114,8 @@ struct CountValues {
 
 __global__ void set_counts_kernel(uint32_t* counts, const CountValues vals, int n, unsigned long long* psteps) {
     const int t = threadIdx.x;
-    if (t < n) counts[t] = vals.v[t];
-    if (t < NSEG && psteps) psteps[t] = 0ull;
+    if (t < n) counts[t * CSTRIDE] = vals.v[t];
+    if (t < NSEG && psteps) psteps[t * PSTRIDE] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(BLOCK) void flowmap_live_kernel(const FlowmapArgs a
     const int seg = blockIdx.x % NSEG;
     const int r = blockIdx.x / NSEG;
     const int R = gridDim.x / NSEG;
-    const uint32_t cnt = a.count[seg];
+    const uint32_t cnt = a.count[seg * CSTRIDE];
     const int64_t sbase = a.segs.base[seg];
     for (uint32_t i = (uint32_t)r * BLOCK + threadIdx.x; i < cnt; i += (uint32_t)R * BLOCK) {
         const uint32_t id = a.id[sbase + i];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(BLOCK) void ckpt_store_kernel(const CkptArgs a) {
     const int seg = blockIdx.x % NSEG;
     const int r = blockIdx.x / NSEG;
     const int R = gridDim.x / NSEG;
-    const uint32_t cnt = a.count[seg];
+    const uint32_t cnt = a.count[seg * CSTRIDE];
     const int64_t sbase = a.segs.base[seg];
     for (uint32_t i = (uint32_t)r * BLOCK + threadIdx.x; i < cnt; i += (uint32_t)R * BLOCK) {
         const uint32_t id = a.id[sbase + i];

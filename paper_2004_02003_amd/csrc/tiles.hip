@@ -138,8 +138,8 @@ __device__ __forceinline__ void add_totals(uint32_t steps, uint32_t surv, unsign
             tl += s_red[NT / WAVE + w];
         }
         const int xcd = blockIdx.x % NSEG;
-        if (ts) atomicAdd(&psteps[xcd], ts);
-        if (tl) atomicAdd(&live[xcd], tl);
+        if (ts) atomicAdd(&psteps[xcd * PSTRIDE], ts);
+        if (tl) atomicAdd(&live[xcd * CSTRIDE], tl);
     }
 }
 
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(NT) void tile_gather_kernel(const TileStepArgs a) {
     __shared__ uint32_t s_hist[32], s_base[32];
     __shared__ int32_t s_nb[32];
     __shared__ SortLds<NT> s_sort;
-    if (blockIdx.x == 0 && threadIdx.x < NSEG) a.live_clear[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < NSEG) a.live_clear[threadIdx.x * CSTRIDE] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == NSEG) *a.list_clear = 0u;
     // bucket b = this workgroup: its tile, count and first particles load at once
     const uint32_t b = blockIdx.x;
@@ -454,7 +454,7 @@ __global__ __launch_bounds__(BLOCK) void tile_stage_kernel(const TileStepArgs a)
     __shared__ uint32_t s_hist[32], s_base[32];
     __shared__ int32_t s_nb[32];
     using SR = StageRegs<DT, MODE, S>;
-    if (blockIdx.x == 0 && threadIdx.x < NSEG) a.live_clear[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < NSEG) a.live_clear[threadIdx.x * CSTRIDE] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == NSEG) *a.list_clear = 0u;
     const uint32_t b = blockIdx.x;
     const int32_t t = a.order[b];
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(BLOCK) void tile_bin_kernel(const TileBinArgs a) {
     const int seg = blockIdx.x % NSEG;
     const int r = blockIdx.x / NSEG;
     const int R = gridDim.x / NSEG;
-    const uint32_t cnt = a.count[seg];
+    const uint32_t cnt = a.count[seg * CSTRIDE];
     const int64_t sbase = a.segs.base[seg];
     for (uint32_t b0 = (uint32_t)r * BLOCK; b0 < cnt; b0 += (uint32_t)R * BLOCK) {
         const uint32_t i = b0 + threadIdx.x;
