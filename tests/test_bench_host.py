@@ -1,7 +1,9 @@
 """Host-side logic of bench.py (no GPU): the launch plan mirrors the library's
 balanced split, the algorithmic-bytes model is the stated per-unit figure,
-the per-workload launch shapes name real workloads, and the entry point
-refuses more than one GPU before touching a device."""
+the per-workload launch shapes name real workloads, the entry point
+refuses more than one GPU before touching a device, and the committed
+headline line's roofline follows from its own fields and the counter record
+of the current kernel sources."""
 
 import importlib.util
 import os
@@ -107,3 +109,30 @@ def test_adjoint_byte_model_from_touched_points(bench):
         2 * pts * 12 + 48 * live + 24 * 10)
     assert bench.adjoint_alg_bytes(t, "jacobian_ftle", 2, n_seeds=10, n_cot=3) == int(
         3 * pts * 12 + 48 * live + 48 * live / 2 + 24 * 30)
+
+
+def test_committed_bench_line_is_self_consistent(bench):
+    """The committed line of the headline workload: its roofline fraction is
+    the algorithmic bytes per launch (particle-steps per launch x the per-unit
+    figure) over the average launch time, against 8 TB/s; its value is the
+    interval's particle-steps over the interval time; its traffic is the
+    counter record taken on the kernel sources now in the tree."""
+    import json
+
+    line = json.load(open(os.path.join(ROOT, "profiles", "bench_turb512_f16.json")))
+    assert line["n_gpus"] == 1 and line["config"]["workload"] == "turb_512"
+    r = line["roofline"]
+    assert r["bound"] == "hbm" and r["peak"] == 8000.0 and r["unit"] == "GB/s"
+    assert r["bytes_per_particle_step"] == bench.insitu_bytes_per_pstep("f16")
+    alg = r["particle_steps_per_launch"] * r["bytes_per_particle_step"]
+    assert abs(alg - r["algorithmic_bytes_per_launch"]) <= 1e-6 * alg + 1
+    achieved = r["algorithmic_bytes_per_launch"] / (r["avg_launch_ms"] * 1e-3) / 1e9
+    assert abs(achieved - r["achieved"]) <= 1e-3 * achieved
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) <= 1e-4
+    value = line["config"]["particle_steps_per_interval"] / (line["ms_per_step"] * 1e-3)
+    assert abs(value - line["value"]) <= 1e-3 * value
+    # the traffic came from the counter record of the same kernel sources
+    rec = bench.traffic_record("turb_512", "f16", "insitu")
+    assert rec is not None, "counter record missing or taken on other kernel sources"
+    assert r["traffic"] == rec["bytes_per_launch"]
+    assert os.path.exists(os.path.join(ROOT, "profiles", rec["source"]))
