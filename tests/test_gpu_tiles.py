@@ -12,8 +12,8 @@ other configuration does.  The cases cover slow and fast flows (few and many
 deferred particles), every storage type and both time modes, ragged blocks,
 seeds crowded into a few tiles (bucket overflow into the list), exit points,
 streaming calls, a flow map read in the middle of an interval, recorded
-checkpoints for the adjoint, and the refusal of a storage type with another
-tile size inside one interval."""
+checkpoints for the adjoint, blocks at the largest axis length along each axis,
+and the refusal of a storage type with another tile size inside one interval."""
 
 import sys
 
@@ -122,6 +122,40 @@ def test_tiles_crowded_seeds_overflow_their_buckets():
     g = _pair(n, _dev(gr, "f16"), s.times, "crowded seeds", seeds=seeds)
     o = oracle.flowmap(oracle.Field(n, gr, dtype="f16"), s.times, seeds, N)
     compare(g, o, label="tiles crowded")
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_tiles_at_the_largest_block_axis(axis):
+    """A block 1,024 points long along one axis (the 10-bit cell index of the
+    packed state) in uniform flow along that axis: both tile layouts equal the
+    segment layout, a stride-3 lattice matches the oracle, and seeds over the
+    whole long axis, the last cells included, end at x0 + u t or terminate in
+    the step that would cross the far face, as the closed form says."""
+    n = [12, 10, 9]
+    n[axis] = 1024
+    n = tuple(n)
+    N = 8
+    times = np.arange(N + 1) * 0.25
+    u = np.zeros(3)
+    u[axis] = 3.7
+    s = fields.uniform_flow(n, u, times)
+    gr = s.grids("f32")
+    dev = _dev(gr, "f32")
+    _pair(n, dev, times, f"long axis {axis}: lattice", stride=3)
+    g = run_gpu(n, dev, times, stride=3, tuning=dict(tiles=2))
+    seeds, o = oracle_lattice(oracle.Field(n, gr), times, n, 3, N)
+    compare(g, o, label=f"tiles, long axis {axis}", seeds=seeds, n=n)
+    xs = np.array([0.3, 500.5, 1000.0, 1015.2, 1016.9, 1019.0, 1021.7, 1022.99])
+    seeds = np.tile([[5.5, 4.5, 4.0]], (len(xs), 1))
+    seeds[:, axis] = xs
+    ge = _pair(n, dev, times, f"long axis {axis}: explicit seeds", seeds=seeds)
+    ux = float(np.float32(3.7))
+    for i, x0 in enumerate(xs):
+        ends = x0 + ux * (times[1:] - times[0])
+        inside = ends <= 1023.0
+        e = N if inside.all() else int(np.argmin(inside))
+        assert ge["exit"][i] == e, (axis, x0, ge["exit"][i], e)
+        assert abs(ge["end"][i, axis] - (x0 + ux * (times[e] - times[0]))) < 1e-5
 
 
 def test_tiles_flowmap_mid_interval_and_recorded_checkpoints():
