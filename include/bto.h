@@ -158,7 +158,9 @@ int bto_advect_interval(bto_ctx *ctx, const void *const *d_fields, const double 
  * BTO_TERMINATED / BTO_INVALID), d_exit_step (step of termination, or the
  * interval's step count for valid seeds).  If n_valid_out is non-NULL the call
  * synchronizes `stream` and returns the number of valid seeds.  The particle
- * state is left unchanged (more steps may follow). */
+ * state is left unchanged (more steps may follow).  An interval seeded with
+ * no seeds writes nothing, and its output pointers may then be NULL.
+ * BTO_ESTATE before seeding. */
 int bto_flowmap_out(bto_ctx *ctx, double *d_seed_xyz, double *d_end_xyz, uint8_t *d_flag,
                     int32_t *d_exit_step, int64_t *n_valid_out, void *stream);
 
@@ -172,7 +174,7 @@ int bto_flowmap_out(bto_ctx *ctx, double *d_seed_xyz, double *d_end_xyz, uint8_t
  * d_exit_xyz: n x 3 doubles on the device, written on `stream` (async);
  * NaN for valid and invalid seeds, for seeds outside the block at seeding
  * and for particles terminated by a call made without BTO_RECORD_EXIT.
- * BTO_ESTATE before seeding. */
+ * May be NULL for an interval without seeds.  BTO_ESTATE before seeding. */
 int bto_exit_points(bto_ctx *ctx, double *d_exit_xyz, void *stream);
 
 /* Counters of the current interval.  Synchronizes `stream`. */
@@ -250,6 +252,7 @@ int bto_get_tuning(const bto_ctx *ctx, bto_tuning *t);
  *              3 (one per axis: d_grad_seed then holds the 3x3 flow-map
  *              Jacobian dx_end/dx_0 per seed, row-major).
  *   d_grad_seed (n_seeds x n_cot x 3 floats): d L / d x_0 per cotangent.
+ *              (d_cot_end and d_grad_seed may be NULL when n_seeds is 0.)
  *   d_grad_fields: NULL, or a HOST array of n_steps + 1 device pointers to
  *              float32 grids shaped like the velocity grids (non-overlapping;
  *              if one pointer repeats, the atomic path below is used);

@@ -791,8 +791,9 @@ int bto_flowmap_out(bto_ctx* c, double* d_seed_xyz, double* d_end_xyz, uint8_t* 
                     int64_t* n_valid_out, void* stream) {
     int rc = begin(c);
     if (rc) return rc;
-    if (!d_end_xyz || !d_flag || !d_exit_step) return fail(c, BTO_EINVAL, "null output pointer");
     if (!c->seeded) return fail(c, BTO_ESTATE, "flowmap_out called before seeding");
+    // an interval without seeds writes nothing: its (empty) outputs may be null
+    if (c->n_seeds > 0 && (!d_end_xyz || !d_flag || !d_exit_step)) return fail(c, BTO_EINVAL, "null output pointer");
     hipStream_t s = (hipStream_t)stream;
     if (c->n_seeds > 0) {
         FlowmapArgs a{};
@@ -835,8 +836,8 @@ int bto_flowmap_out(bto_ctx* c, double* d_seed_xyz, double* d_end_xyz, uint8_t* 
 int bto_exit_points(bto_ctx* c, double* d_exit_xyz, void* stream) {
     int rc = begin(c);
     if (rc) return rc;
-    if (!d_exit_xyz) return fail(c, BTO_EINVAL, "null output pointer");
     if (!c->seeded) return fail(c, BTO_ESTATE, "exit_points called before seeding");
+    if (c->n_seeds > 0 && !d_exit_xyz) return fail(c, BTO_EINVAL, "null output pointer");
     if (c->n_seeds > 0) {
         FlowmapArgs a{};
         a.P = c->n_seeds;
@@ -1104,7 +1105,7 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
                          float* const* d_grad_fields, uint8_t* d_status, int32_t ckpt_every, void* stream) {
     int rc = begin(c);
     if (rc) return rc;
-    if (!d_fields || !times || !d_cot_end || !d_grad_seed) return fail(c, BTO_EINVAL, "null argument");
+    if (!d_fields || !times) return fail(c, BTO_EINVAL, "null field or time array");
     if (n_steps <= 0) return fail(c, BTO_EINVAL, "n_steps must be > 0 (got %d)", n_steps);
     if (dtype < BTO_F32 || dtype > BTO_BF16) return fail(c, BTO_EINVAL, "unknown dtype %d", dtype);
     const int mode = flags & ~BTO_RECORD_CKPT;
@@ -1121,6 +1122,8 @@ int bto_adjoint_interval(bto_ctx* c, const void* const* d_fields, const double* 
         if (!(times[q + 1] > times[q]) || !std::isfinite(times[q + 1]) || !std::isfinite(times[q]))
             return fail(c, BTO_EINVAL, "times must be finite and strictly increasing (index %d)", q);
     if (!c->seeded) return fail(c, BTO_ESTATE, "adjoint called before seeding");
+    // per-seed arrays may be null only when there are no seeds
+    if (c->n_seeds > 0 && (!d_cot_end || !d_grad_seed)) return fail(c, BTO_EINVAL, "null cotangent or gradient array");
     if (use_ck) {
         if (!c->ck_ok || c->ck_k == 0)
             return fail(c, BTO_ESTATE, "no complete checkpoint record (advect every call of the interval with BTO_RECORD_CKPT)");
@@ -1157,12 +1160,13 @@ int bto_adjoint_segment(bto_ctx* c, int32_t segment, const void* const* d_fields
     if (segment < 0 || segment >= nseg) return fail(c, BTO_EINVAL, "segment %d outside 0..%d", segment, nseg - 1);
     const bool first = segment == nseg - 1;
     if (first) {
-        if (!d_cot_end) return fail(c, BTO_EINVAL, "the last segment needs the end cotangents");
+        if (!d_cot_end && c->n_seeds > 0) return fail(c, BTO_EINVAL, "the last segment needs the end cotangents");
     } else if (c->seg_next != segment || c->seg_ncot != n_cot) {
         return fail(c, BTO_ESTATE, "segments must be swept from %d down to 0 with one n_cot (expected %d)", nseg - 1,
                     c->seg_next);
     }
-    if (segment == 0 && !d_grad_seed) return fail(c, BTO_EINVAL, "segment 0 needs the seed-gradient output");
+    if (segment == 0 && !d_grad_seed && c->n_seeds > 0)
+        return fail(c, BTO_EINVAL, "segment 0 needs the seed-gradient output");
     const int n0 = segment * K, n1 = n0 + K < N ? n0 + K : N;
     const int nl = n1 - n0;
     for (int32_t q = 0; q <= nl; ++q) {

@@ -13,7 +13,8 @@ deferred particles), every storage type and both time modes, ragged blocks,
 seeds crowded into a few tiles (bucket overflow into the list), exit points,
 streaming calls, a flow map read in the middle of an interval, recorded
 checkpoints for the adjoint, blocks at the largest axis length along each axis,
-and the refusal of a storage type with another tile size inside one interval."""
+intervals without live particles, and the refusal of a storage type with
+another tile size inside one interval."""
 
 import sys
 
@@ -156,6 +157,42 @@ def test_tiles_at_the_largest_block_axis(axis):
         e = N if inside.all() else int(np.argmin(inside))
         assert ge["exit"][i] == e, (axis, x0, ge["exit"][i], e)
         assert abs(ge["end"][i, axis] - (x0 + ux * (times[e] - times[0]))) < 1e-5
+
+
+def test_intervals_without_live_particles():
+    """Degenerate intervals in each layout: seeds that all lie outside the
+    block (terminated at step 0 where they were placed, no exit point, no
+    particle-step counted), and no seeds at all (empty flow map, exit points
+    and seed gradients, with the empty tensors' null data pointers)."""
+    import torch
+    from paper_2004_02003_amd import Context
+
+    n = (40, 20, 18)
+    N = 6
+    s = fields.abc_noise(n, N + 1, 0.1, sigma=0.0, seed=3, global_n=48)
+    gr = s.grids("f16")
+    dev = _dev(gr, "f16")
+    outside = np.array([[-0.5, 3, 3], [39.01, 5, 5], [5, -2, 5], [5, 5, 17.5], [1e9, 0, 0]], dtype=np.float64)
+    for tiles in (0, 1, 2):
+        tuning = dict(tiles=tiles) if tiles else dict(steps_per_launch=1)
+        _say(f"no live particles, tiles={tiles}")
+        g = run_gpu(n, dev, s.times, seeds=outside, tuning=tuning, record_exit=True)
+        assert np.all(g["flag"] == 1) and np.all(g["exit"] == 0)
+        assert np.array_equal(g["end"], outside)
+        assert np.all(np.isnan(g["face"]))
+        assert g["stats"]["particle_steps"] == 0 and g["n_valid"] == 0
+        with Context(n, 1) as ctx:
+            ctx.set_tuning(**tuning)
+            assert ctx.seed_explicit(torch.empty((0, 3), dtype=torch.float64, device="cuda")) == 0
+            ctx.advect(dev, s.times)
+            fm = ctx.flowmap(count_valid=True)
+            assert tuple(fm["end"].shape) == (0, 3) and fm["n_valid"] == 0
+            assert tuple(ctx.exit_points().shape) == (0, 3)
+            gs = ctx.adjoint(dev, s.times, torch.empty((0, 1, 3), dtype=torch.float32, device="cuda"))
+            assert gs.shape[0] == 0
+            st = ctx.stats()
+            torch.cuda.synchronize()
+            assert st["particle_steps"] == 0 and st["n_live"] == 0 and st["steps_done"] == N
 
 
 def test_tiles_flowmap_mid_interval_and_recorded_checkpoints():
