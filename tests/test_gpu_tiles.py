@@ -13,7 +13,7 @@ deferred particles), every storage type and both time modes, ragged blocks,
 seeds crowded into a few tiles (bucket overflow into the list), exit points,
 streaming calls, a flow map read in the middle of an interval, recorded
 checkpoints for the adjoint, blocks at the largest axis length along each axis,
-intervals without live particles, and the refusal of a storage type with
+uneven step sizes, intervals without live particles, and the refusal of a storage type with
 another tile size inside one interval."""
 
 import sys
@@ -157,6 +157,32 @@ def test_tiles_at_the_largest_block_axis(axis):
         e = N if inside.all() else int(np.argmin(inside))
         assert ge["exit"][i] == e, (axis, x0, ge["exit"][i], e)
         assert abs(ge["end"][i, axis] - (x0 + ux * (times[e] - times[0]))) < 1e-5
+
+
+def test_tiles_non_uniform_steps_closed_form():
+    """Uneven step sizes (one h per step call) in uniform flow: both tile
+    layouts equal the segment layout, match the oracle, end valid particles at
+    x0 + u (t_N - t_0), and place exit points where the straight line leaves
+    the block."""
+    rng = np.random.default_rng(11)
+    n = (44, 21, 19)
+    N = 24
+    times = np.concatenate([[0.5], 0.5 + np.cumsum(rng.uniform(0.2, 0.9, N))])
+    u = np.array([1.3, -0.35, 0.4])
+    s = fields.uniform_flow(n, u, times)
+    gr = s.grids("f32")
+    g = _pair(n, _dev(gr, "f32"), times, "uneven steps", stride=2, record_exit=True)
+    seeds, o = oracle_lattice(oracle.Field(n, gr), times, n, 2, N)
+    res = compare(g, o, label="tiles uneven steps", seeds=seeds, n=n)
+    assert 0.0 < res["terminated"] < 1.0
+    valid = g["flag"] == oracle.VALID
+    np.testing.assert_allclose(g["end"][valid], seeds[valid] + u * (times[-1] - times[0]), atol=1e-5)
+    hi = np.array(n, dtype=float) - 1
+    t_face = np.where(u > 0, (hi - seeds) / u, np.where(u < 0, -seeds / u, np.inf))
+    t_sorted = np.sort(t_face, axis=1)
+    term = (g["flag"] == oracle.TERMINATED) & (t_sorted[:, 1] - t_sorted[:, 0] > 1e-6)
+    assert term.sum() > 100
+    np.testing.assert_allclose(g["face"][term], (seeds + u * t_sorted[:, :1])[term], atol=1e-5)
 
 
 def test_intervals_without_live_particles():
