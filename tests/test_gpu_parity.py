@@ -200,15 +200,27 @@ def test_world_coordinates_origin_and_spacing():
     spacing = np.array([0.5, 2.0, 0.25])
     # a grid in world units per time: cell velocity times spacing
     grw = [(quant.promote(g, "f32") * spacing).astype(np.float32) for g in gr]
-    _say("origin/spacing 20x16x12")
-    g = run_gpu(n, _dev(grw, "f32"), s.times, stride=2, origin=origin, spacing=spacing, record_exit=True)
     cells = [(quant.promote(g2, "f32") / spacing) for g2 in grw]
     _, o = oracle_lattice(oracle.Field(n, cells), s.times, n, 2, N)
-    g_cells = dict(g)
-    g_cells["end"] = (g["end"] - origin) / spacing
-    g_cells["face"] = (g["face"] - origin) / spacing
-    compare(g_cells, o, label="world")
-    np.testing.assert_allclose((g["seed"] - origin) / spacing, oracle.seed_lattice(n, 2), atol=0)
+    dev = _dev(grw, "f32")
+    one_step = None
+    # every layout writes world coordinates: fused segments, one step per
+    # launch, and both tile layouts (their own flow-map writer), which equal
+    # the one-step segment run bit for bit
+    for tuning in (None, dict(steps_per_launch=1), dict(tiles=1), dict(tiles=2)):
+        _say(f"origin/spacing 20x16x12 {tuning}")
+        g = run_gpu(n, dev, s.times, stride=2, origin=origin, spacing=spacing, record_exit=True, tuning=tuning)
+        g_cells = dict(g)
+        g_cells["end"] = (g["end"] - origin) / spacing
+        g_cells["face"] = (g["face"] - origin) / spacing
+        compare(g_cells, o, label=f"world {tuning}")
+        np.testing.assert_allclose((g["seed"] - origin) / spacing, oracle.seed_lattice(n, 2), atol=0)
+        if tuning == dict(steps_per_launch=1):
+            one_step = g
+        elif tuning is not None:
+            for k in ("flag", "exit", "end"):
+                assert np.array_equal(g[k], one_step[k]), (tuning, k)
+            assert np.array_equal(g["face"], one_step["face"], equal_nan=True), tuning
 
 
 def test_nonfinite_velocity_flags_invalid_on_gpu():
