@@ -229,11 +229,14 @@ def test_nonfinite_velocity_flags_invalid_on_gpu():
     gs = s.grids("f32")
     gs[2][5, 5, 5] = np.nan
     seeds = np.array([[4.0, 5.0, 5.0], [4.0, 2.0, 2.0]])
-    _say("nan field")
-    g = run_gpu(n, _dev(gs, "f32"), s.times, seeds=seeds)
-    assert g["flag"].tolist() == [2, 0] and g["exit"][0] == 1
-    assert np.all(np.isfinite(g["end"]))
-    np.testing.assert_allclose(g["end"][0], [4.1, 5.0, 5.0], atol=1e-6)
+    dev = _dev(gs, "f32")
+    for tuning in (None, dict(tiles=1), dict(tiles=2)):  # every layout
+        _say(f"nan field {tuning}")
+        g = run_gpu(n, dev, s.times, seeds=seeds, tuning=tuning)
+        assert g["flag"].tolist() == [2, 0] and g["exit"][0] == 1, tuning
+        assert np.all(np.isfinite(g["end"]))
+        np.testing.assert_allclose(g["end"][0], [4.1, 5.0, 5.0], atol=1e-6)
+        assert g["stats"]["particle_steps"] == 2 + len(s.times) - 1, tuning  # the INVALID step counts
 
 
 def test_abc_128_full_size_sampled_parity():
