@@ -189,6 +189,16 @@ def test_explicit_seeds_including_outside_and_permutation():
     assert np.array_equal(gp["exit"], g["exit"][perm])
     assert np.array_equal(gp["end"], g["end"][perm])
     assert np.array_equal(gp["face"], g["face"][perm], equal_nan=True)
+    # the gathering tile layout bins the same seeds by tile: same parity,
+    # and its flow map is just as independent of the seed order
+    _say("explicit seeds, gathering tiles (and permuted)")
+    gt = run_gpu(n, _dev(gr, "f32"), s.times, seeds=seeds, record_exit=True, tuning=dict(tiles=2))
+    compare(gt, o, label="explicit, tiles")
+    assert np.array_equal(gt["flag"][outside], g["flag"][outside]) and np.array_equal(gt["end"][outside], seeds[outside])
+    gtp = run_gpu(n, _dev(gr, "f32"), s.times, seeds=seeds[perm], record_exit=True, tuning=dict(tiles=2))
+    for k in ("flag", "exit", "end"):
+        assert np.array_equal(gtp[k], gt[k][perm]), k
+    assert np.array_equal(gtp["face"], gt["face"][perm], equal_nan=True)
 
 
 def test_world_coordinates_origin_and_spacing():
