@@ -112,8 +112,7 @@ __device__ __forceinline__ void acc_flush(const Geom& g, float* const* gf, const
         const uint32_t i = A.base % g.sy, j = (A.base / g.sy) % (uint32_t)g.n[1], k = A.base / g.sz;
         const uint64_t colour = (uint64_t)((i & 1u) | ((j & 1u) << 1) | ((k & 1u) << 2));
         R.key[slot] = (colour << (R.level_bits + R.cell_bits)) | ((uint64_t)A.level << R.cell_bits) |
-                      (uint64_t)A.base;
-        R.idx[slot] = (uint32_t)slot;
+                      (uint64_t)A.base;  // the slot's sort value, its index, was written by the clear
         float4* out = reinterpret_cast<float4*>(R.val + 24 * (size_t)slot);
 #pragma unroll
         for (int q = 0; q < 6; ++q)

@@ -18,9 +18,14 @@
 
 namespace bto {
 
-__global__ __launch_bounds__(BLOCK) void grad_clear_kernel(uint64_t* key, uint64_t n, uint64_t empty) {
-    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (uint64_t)gridDim.x * BLOCK)
+// Before a sweep: every slot unused, and each slot's sort value its own index
+// (written here in one coalesced pass rather than by the sweep's scattered
+// record stores).
+__global__ __launch_bounds__(BLOCK) void grad_clear_kernel(uint64_t* key, uint32_t* idx, uint64_t n, uint64_t empty) {
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (uint64_t)gridDim.x * BLOCK) {
         key[i] = empty;
+        idx[i] = (uint32_t)i;
+    }
 }
 
 // bounds[c] = first sorted slot of colour c (c = 0..8; colour 8 = unused slots).
@@ -87,7 +92,7 @@ static unsigned grid_of(uint64_t n) {
 hipError_t launch_grad_clear(const GradRec& r, uint64_t n, hipStream_t s) {
     // unused slots: the colour field reads 8, above every real colour
     const uint64_t empty = (uint64_t)8 << (key_bits(r) - 3);
-    hipLaunchKernelGGL(grad_clear_kernel, dim3(grid_of(n)), dim3(BLOCK), 0, s, r.key, n, empty);
+    hipLaunchKernelGGL(grad_clear_kernel, dim3(grid_of(n)), dim3(BLOCK), 0, s, r.key, r.idx, n, empty);
     return hipGetLastError();
 }
 
