@@ -697,7 +697,7 @@ def turb_storage_legs(log, copy_gbs, steps=3, warmup=1):
                    "interval_ms": round(m["interval_ms_median"], 4), "particle_steps": m["particle_steps"],
                    "valid_at_end": m["valid_at_end"],
                    "roofline": roofline_of(m, dt, wl.name, "insitu_fp64" if fp64 else "insitu",
-                                           f"tile_gather_kernel<{dt},linear{',fp64 sampling' if fp64 else ''}> + "
+                                           f"tile_gather_kernel<{dt},linear{',extended-precision sampling' if fp64 else ''}> + "
                                            f"tile_list_kernel (one step per call)", copy_gbs),
                    "tuning": m["tuning"]}
             # fused: all grids resident, several steps per launch (segment layout,
@@ -718,7 +718,7 @@ def turb_storage_legs(log, copy_gbs, steps=3, warmup=1):
                                          "advect_ms": round(float(np.median(ts)), 4), "tuning": ctx.tuning(),
                                          "one_level_model_bytes_per_particle_step": 8 * field_bytes_per_point(dt)}
         if fp64:
-            rec["sampler"] = "fp64 (BTO_SAMPLE_FP64)"
+            rec["sampler"] = "extended precision (BTO_SAMPLE_FP64: FP64 sums and stage velocities, FP32 weights on corner differences)"
         out[key] = rec
         log(f"turb_256 {key}: in situ {rec['value']:.3e}, fused {rec['fused_all_resident']['value']:.3e} "
             f"particle-steps/s")
@@ -853,7 +853,8 @@ def cpu_reference_errors(gpu, threads, log):
     max over the seeds valid on both sides, the share beyond 1e-5 cells) and
     the first-order bound ||J|| N h max|V| sqrt(3) (u_storage + 2^-21) per seed
     (J from the oracle's tangent, u the storage's unit roundoff, 2^-21 the FP32
-    sampling, 2^-50 with FP64 sampling)."""
+    sampling, kept for the extended-precision sampler, whose FP32 sums run over
+    corner differences)."""
     import oracle
 
     out = {}
@@ -871,7 +872,7 @@ def cpu_reference_errors(gpu, threads, log):
             both = (flag == 0) & (o["flag"] == 0)
             err = np.linalg.norm(end[both] - o["end"][both], axis=1)
             bound = (nJ[both] * N * wl.dt * r["vmax"] * np.sqrt(3.0) *
-                     (UNIT_ROUNDOFF[r["dt"]] + (2.0 ** -50 if r["fp64"] else 2.0 ** -21)))
+                     (UNIT_ROUNDOFF[r["dt"]] + 2.0 ** -21))
             res[key] = {"mean": float(err.mean()), "p99": float(np.quantile(err, 0.99)), "max": float(err.max()),
                         "n": int(both.sum()), "beyond_1e-5_pct": round(100.0 * float((err > 1e-5).mean()), 3),
                         "within_first_order_bound_pct": round(100.0 * float((err <= bound).mean()), 2),

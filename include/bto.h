@@ -77,12 +77,16 @@ enum { BTO_RECORD_EXIT = 2 };
  * one ckpt_every). */
 enum { BTO_RECORD_CKPT = 1 << 4 };
 
-/* Flag bit of bto_advect_interval: sample the field in FP64 -- in-cell
- * offsets, trilinear weights, the weighted sums and the stage velocities --
- * instead of FP32 (grid values and positions are unchanged: the stored values
- * and FP64 positions).  Lowers the sampler's rounding below the FP32 grid
- * values' own, at more ALU work per step; lanes_per_particle 2 does not apply.
- * The adjoint always samples in FP32 (it rejects the flag). */
+/* Flag bit of bto_advect_interval: extended-precision sampling.  In-cell
+ * offsets, the interpolation sums and the stage velocities are FP64; the
+ * trilinear weights are applied in FP32 to the differences of the corner
+ * values from the cell's base corner, which enters the FP64 sum with
+ * coefficient 1 (grid values and positions are unchanged: the stored values
+ * and FP64 positions).  The sampler's rounding then scales with the field's
+ * variation across a cell instead of its magnitude, close to a sampler
+ * entirely in FP64, at a few more ALU operations per step;
+ * lanes_per_particle 2 does not apply.  The adjoint always samples in FP32
+ * (it rejects the flag). */
 enum { BTO_SAMPLE_FP64 = 1 << 5 };
 
 /* Per-seed outcome in the flow map. */

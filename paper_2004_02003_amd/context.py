@@ -139,7 +139,8 @@ class Context:
         ``record_exit`` keeps the exit point of every particle terminated here
         (``exit_points``); ``record_ckpt`` records checkpoints every
         ``tuning()["ckpt_every"]`` steps for ``adjoint(..., recorded=True)``;
-        ``fp64`` samples the field in FP64 (BTO_SAMPLE_FP64)."""
+        ``fp64`` samples the field in extended precision (BTO_SAMPLE_FP64: FP64
+        sums and stage velocities over FP32-weighted corner differences)."""
         if len(grids) < 2:
             raise ValueError("need at least two grids (one step)")
         dt = grids[0].dtype

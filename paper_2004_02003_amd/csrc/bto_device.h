@@ -37,8 +37,9 @@ constexpr int S_DEFER = 3;
 constexpr int ADJ_DROPPED = 3, ADJ_DROPPED_PARTIAL = 4;
 enum : int { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
 enum : int { MODE_LINEAR = 0, MODE_FROZEN = 1 };
-// Mode bit: the sampler (in-cell offsets, weights, weighted sums, stage
-// velocities) in FP64 instead of FP32.
+// Mode bit: extended-precision sampling.  In-cell offsets, sums and stage
+// velocities in FP64; trilinear weights applied in FP32 to the corner
+// differences from the cell's base corner (trilerp / trilerp_mid for double).
 constexpr int MODE_FP64 = 2;
 template <int MODE>
 constexpr bool is_frozen = (MODE & MODE_FROZEN) != 0;
@@ -242,6 +243,50 @@ __device__ __forceinline__ void trilerp(const CA& A, const R f[3], R out[3]) {
             acc = fmar(w[r][1], (R)A.v(r, 3 + c), acc);
         }
         out[c] = acc;
+    }
+}
+
+// The extended-precision sampler (MODE_FP64, R = double).  The weights and
+// the corner differences stay in FP32; the base corner, the sum and the stage
+// velocity are FP64: v = b + sum_i w_i (v_i - b) with b the cell's first
+// corner.  The base enters with coefficient exactly 1, so the weights' and
+// the sum's rounding scale with the differences across the cell, not with the
+// velocity itself -- close to a sampler entirely in FP64 at a fraction of its
+// conversions and registers.
+template <class CA>
+__device__ __forceinline__ void trilerp(const CA& A, const double f[3], double out[3]) {
+    const float ff[3] = {(float)f[0], (float)f[1], (float)f[2]};
+    float w[4][2];
+    corner_weights<float>(ff, 1.f, w);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float b = A.v(0, c);
+        float acc = w[0][1] * (A.v(0, 3 + c) - b);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            acc = fmaf(w[r][0], A.v(r, c) - b, acc);
+            acc = fmaf(w[r][1], A.v(r, 3 + c) - b, acc);
+        }
+        out[c] = (double)b + (double)acc;
+    }
+}
+
+// The same at the time midpoint: base (b_A + b_B) / 2, differences of both levels.
+template <class CA>
+__device__ __forceinline__ void trilerp_mid(const CA& A, const CA& B, const double f[3], double out[3]) {
+    const float ff[3] = {(float)f[0], (float)f[1], (float)f[2]};
+    float w[4][2];
+    corner_weights<float>(ff, 0.5f, w);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float ba = A.v(0, c), bb = B.v(0, c);
+        float acc = w[0][1] * ((A.v(0, 3 + c) - ba) + (B.v(0, 3 + c) - bb));
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            acc = fmaf(w[r][0], (A.v(r, c) - ba) + (B.v(r, c) - bb), acc);
+            acc = fmaf(w[r][1], (A.v(r, 3 + c) - ba) + (B.v(r, 3 + c) - bb), acc);
+        }
+        out[c] = 0.5 * ((double)ba + (double)bb) + (double)acc;
     }
 }
 

@@ -147,7 +147,8 @@ def test_turb_256_precision_workload_sampled_parity():
 
 
 def test_turb_256_fp32_grids_sampled_in_fp64_meet_a_flat_1e5():
-    """FP32 grids sampled in FP64 (BTO_SAMPLE_FP64): every sampled seed of the
+    """FP32 grids sampled in extended precision (BTO_SAMPLE_FP64: FP64 sums and
+    stage velocities over FP32-weighted corner differences): every sampled seed of the
     256^3 precision workload that is valid on both sides ends within a flat
     1e-5 cells of the FP64 oracle on the same stored values (the FP32 sampler
     needs the Jacobian-stretched bound for 0.4-0.5% of them), with the same
