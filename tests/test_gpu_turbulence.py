@@ -164,7 +164,7 @@ def test_turb_256_fp32_grids_sampled_in_fp64_meet_a_flat_1e5():
     o = oracle.flowmap(oracle.Field.lazy_turbulence(s, "f32"), s.times, seeds, wl.n_steps)
     grids = [dev.fill(c, "f32", _empty(s.n, "f32")) for c in range(wl.n_steps + 1)]
     for tune in (dict(), dict(tiles=2)):
-        _say(f"{wl.name} f32 sampled in FP64 {tune}")
+        _say(f"{wl.name} f32, extended-precision sampling {tune}")
         with Context(wl.n, wl.n_seeds) as ctx:
             ctx.set_tuning(**tune)
             ctx.seed(wl.stride)
